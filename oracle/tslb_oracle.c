@@ -1,0 +1,572 @@
+/*
+ * FP64 CPU oracle for the moment-only, high-order thread-safe lattice
+ * Boltzmann update (Montessori et al., "High-order thread-safe lattice
+ * Boltzmann model for HPC turbulent flow simulations", arXiv:2401.17074).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This library is the plain, slow, obviously
+ * correct definition the GPU path is checked against.  Only the test suite,
+ * the smoke check and the CPU-baseline leg of the benchmark may load it; the
+ * product path never does.  It shares no code, header, table or constant
+ * with the HIP library.
+ *
+ * Every population is evaluated from the explicit Hermite-tensor formulas
+ * (Section 2.2) in double precision; moments are plain sums over the 27
+ * velocities.  Derivatives (for the adjoint and tangent checks) are taken by
+ * the complex-step method on the very same formulas.
+ *
+ * State layout (all arrays double, SoA, x fastest):
+ *   st[q*N + n], n = x + nx*(y + ny*z), q = 0 rho, 1..3 u, 4..9 Pi^neq
+ *   with Pi ordered xx, yy, zz, xy, xz, yz.
+ */
+#include <complex.h>
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define NQ 27
+static const double CS2 = 1.0 / 3.0; /* lattice sound speed squared, Eq. (lbequil) */
+
+/* ------------------------------------------------------------------ */
+/* D3Q27 lattice (Section 2.1, the D3Q27 figure).  The weights are not
+ * printed in the paper; they are the tensor product of the one-dimensional
+ * three-point Gauss-Hermite weights W(0) = 2/3, W(+-1) = 1/6, the unique
+ * set giving the isotropy the text relies on (sum w c c = cs2 delta up to
+ * the sixth-order moment sum w cx^2 cy^2 cz^2 = cs2^3).                     */
+static int OC[NQ][3];
+static double OW[NQ];
+static int OPP[NQ];
+static const int PI_IDX[3][3] = {{0, 3, 4}, {3, 1, 5}, {4, 5, 2}};
+
+static void lattice_init(void)
+{
+    static int done = 0;
+    if (done) return;
+    int i = 0;
+    for (int cx = -1; cx <= 1; cx++)
+        for (int cy = -1; cy <= 1; cy++)
+            for (int cz = -1; cz <= 1; cz++) {
+                OC[i][0] = cx;
+                OC[i][1] = cy;
+                OC[i][2] = cz;
+                double w = 1.0;
+                for (int a = 0; a < 3; a++) w *= (OC[i][a] == 0) ? 2.0 / 3.0 : 1.0 / 6.0;
+                OW[i] = w;
+                i++;
+            }
+    for (int a = 0; a < NQ; a++)
+        for (int b = 0; b < NQ; b++)
+            if (OC[a][0] == -OC[b][0] && OC[a][1] == -OC[b][1] && OC[a][2] == -OC[b][2]) OPP[a] = b;
+    done = 1;
+}
+
+static double hermite1(int i, int a) { return (double)OC[i][a]; }
+
+static double hermite2(int i, int a, int b)
+{
+    return (double)(OC[i][a] * OC[i][b]) - CS2 * (a == b);
+}
+
+static double hermite3(int i, int a, int b, int g)
+{
+    return (double)(OC[i][a] * OC[i][b] * OC[i][g]) -
+           CS2 * (OC[i][g] * (a == b) + OC[i][a] * (b == g) + OC[i][b] * (a == g));
+}
+
+/* ------------------------------------------------------------------ */
+/* Grid, faces and node classes.                                       */
+enum { FACE_PERIODIC = 0, FACE_WALL = 1, FACE_INLET = 2, FACE_OUTLET = 3 };
+enum { NODE_FLUID = 0, NODE_SOLID = 1, NODE_GHOST = 2 };
+
+typedef struct {
+    int nx, ny, nz;
+    int face[6]; /* -x, +x, -y, +y, -z, +z */
+    double tau;
+    double force[3]; /* uniform body acceleration (used when no field is given) */
+    double inlet_u[3];
+    double inlet_center[2]; /* transverse coordinates of the inlet disc centre */
+    double inlet_radius;
+    double inlet_noise; /* relative amplitude of the inlet perturbation */
+    uint64_t seed;
+} or_grid;
+
+static int dim(const or_grid *G, int d) { return d == 0 ? G->nx : (d == 1 ? G->ny : G->nz); }
+static int is_ghost_face(int k) { return k == FACE_INLET || k == FACE_OUTLET; }
+
+static void node_coords(const or_grid *G, long n, int x[3])
+{
+    x[0] = (int)(n % G->nx);
+    x[1] = (int)((n / G->nx) % G->ny);
+    x[2] = (int)(n / ((long)G->nx * G->ny));
+}
+
+static long node_index(const or_grid *G, const int x[3])
+{
+    return (long)x[0] + (long)G->nx * ((long)x[1] + (long)G->ny * x[2]);
+}
+
+/* A node on a wall face layer is solid (walls win over ghosts); a node on
+ * an inflow/outflow face layer is a ghost; every other node is fluid.       */
+static int node_kind_xyz(const or_grid *G, const int x[3])
+{
+    int ghost = 0;
+    for (int d = 0; d < 3; d++) {
+        int lo = x[d] == 0, hi = x[d] == dim(G, d) - 1;
+        if ((lo && G->face[2 * d] == FACE_WALL) || (hi && G->face[2 * d + 1] == FACE_WALL)) return NODE_SOLID;
+        if ((lo && is_ghost_face(G->face[2 * d])) || (hi && is_ghost_face(G->face[2 * d + 1]))) ghost = 1;
+    }
+    return ghost ? NODE_GHOST : NODE_FLUID;
+}
+
+static int node_kind(const or_grid *G, long n)
+{
+    int x[3];
+    node_coords(G, n, x);
+    return node_kind_xyz(G, x);
+}
+
+static int grid_has_ghosts(const or_grid *G)
+{
+    for (int f = 0; f < 6; f++)
+        if (is_ghost_face(G->face[f])) return 1;
+    return 0;
+}
+
+/* Index of the upstream node x - c_i (periodic axes wrap); -1 if it is solid. */
+static long upstream(const or_grid *G, const int x[3], int i)
+{
+    int y[3];
+    for (int d = 0; d < 3; d++) {
+        int n = dim(G, d);
+        y[d] = x[d] - OC[i][d];
+        if (G->face[2 * d] == FACE_PERIODIC) y[d] = ((y[d] % n) + n) % n;
+        if (y[d] < 0 || y[d] >= n) return -2; /* cannot happen for a fluid node */
+    }
+    if (node_kind_xyz(G, y) == NODE_SOLID) return -1;
+    return node_index(G, y);
+}
+
+/* Nearest interior node of a ghost node: clamp along each ghost axis. */
+static void interior_neighbour(const or_grid *G, const int x[3], int xf[3])
+{
+    for (int d = 0; d < 3; d++) {
+        xf[d] = x[d];
+        if (x[d] == 0 && is_ghost_face(G->face[2 * d])) xf[d] = 1;
+        if (x[d] == dim(G, d) - 1 && is_ghost_face(G->face[2 * d + 1])) xf[d] = dim(G, d) - 2;
+    }
+}
+
+/* SplitMix64 (Steele, Lea, Flood, OOPSLA 2014): the k-th output (k >= 1) of
+ * the generator seeded with `seed` is mix(seed + k * 0x9e3779b97f4a7c15).   */
+static uint64_t splitmix64_at(uint64_t seed, uint64_t k)
+{
+    uint64_t z = seed + k * 0x9e3779b97f4a7c15ULL;
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ULL;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebULL;
+    return z ^ (z >> 31);
+}
+
+/* Uniform variate in [-1, 1) for (level t, node n, component a): the top 24
+ * bits of output k = 1 + 3 (t N + n) + a.  Exact in binary32 and binary64.  */
+static double inlet_xi(uint64_t seed, long t, long n, long N, int a)
+{
+    uint64_t k = 1ULL + 3ULL * ((uint64_t)t * (uint64_t)N + (uint64_t)n) + (uint64_t)a;
+    uint64_t h = splitmix64_at(seed, k);
+    return ldexp((double)(h >> 40), -24) * 2.0 - 1.0;
+}
+
+/* Imposed velocity of an inlet-disc ghost node at level t (top hat plus the
+ * seeded perturbation); returns 0 if the node is not on an inlet disc.      */
+static int inlet_velocity(const or_grid *G, const int x[3], long n, long t, double ub[3])
+{
+    const long N = (long)G->nx * G->ny * G->nz;
+    for (int f = 0; f < 6; f++) {
+        if (G->face[f] != FACE_INLET) continue;
+        int d = f / 2;
+        int layer = (f % 2 == 0) ? 0 : dim(G, d) - 1;
+        if (x[d] != layer) continue;
+        int d1 = (d + 1) % 3, d2 = (d + 2) % 3;
+        if (d1 > d2) { int tmp = d1; d1 = d2; d2 = tmp; }
+        double r1 = x[d1] - G->inlet_center[0], r2 = x[d2] - G->inlet_center[1];
+        if (r1 * r1 + r2 * r2 > G->inlet_radius * G->inlet_radius) continue;
+        double mag = sqrt(G->inlet_u[0] * G->inlet_u[0] + G->inlet_u[1] * G->inlet_u[1] +
+                          G->inlet_u[2] * G->inlet_u[2]);
+        for (int a = 0; a < 3; a++)
+            ub[a] = G->inlet_u[a] + G->inlet_noise * mag * inlet_xi(G->seed, t, n, N, a);
+        return 1;
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* The arithmetic, instantiated for double and for double complex.     */
+#define R double
+#define FN(name) name##_r
+#include "tslb_core.inc"
+#undef R
+#undef FN
+
+#define R double complex
+#define FN(name) name##_c
+#include "tslb_core.inc"
+#undef R
+#undef FN
+
+static const double CSTEP = 1e-30; /* complex-step size */
+
+/* ------------------------------------------------------------------ */
+/* IEEE 754 round-to-nearest-even into a binary format with `frac` stored
+ * fraction bits, minimum normal exponent `emin` and largest finite `maxv`.
+ * Subnormals use the fixed quantum 2^(emin - frac); overflow gives inf.     */
+static double round_binary(double x, int frac, int emin, double maxv)
+{
+    if (x == 0.0 || !isfinite(x)) return x;
+    double ax = fabs(x);
+    int e;
+    frexp(ax, &e); /* ax = m 2^e, m in [0.5, 1): floor(log2 ax) = e - 1 */
+    int E = e - 1;
+    if (E < emin) E = emin;
+    double q = ldexp(1.0, E - frac);
+    double r = nearbyint(ax / q) * q; /* default rounding mode: ties to even */
+    if (r > maxv) r = INFINITY;
+    return copysign(r, x);
+}
+
+double or_round_fp16(double x) { return round_binary(x, 10, -14, 65504.0); }
+double or_round_bf16(double x) { return round_binary(x, 7, -126, ldexp(255.0, 120)); }
+
+/* ================================================================== */
+/* Exported API (ctypes).                                              */
+
+void or_lattice(int *c, double *w, int *opp)
+{
+    lattice_init();
+    for (int i = 0; i < NQ; i++) {
+        for (int a = 0; a < 3; a++) c[3 * i + a] = OC[i][a];
+        w[i] = OW[i];
+        opp[i] = OPP[i];
+    }
+}
+
+/* Hermite tensor component of order `order` (0..3) at velocity i. */
+double or_hermite(int i, int order, int a, int b, int g)
+{
+    lattice_init();
+    switch (order) {
+    case 0: return 1.0;
+    case 1: return hermite1(i, a);
+    case 2: return hermite2(i, a, b);
+    case 3: return hermite3(i, a, b, g);
+    }
+    return NAN;
+}
+
+double or_feq(int i, double rho, const double *u)
+{
+    lattice_init();
+    return feq_r(i, rho, u);
+}
+
+double or_fneq(int i, const double *pi6, const double *u)
+{
+    lattice_init();
+    double pi[3][3];
+    for (int a = 0; a < 3; a++)
+        for (int b = 0; b < 3; b++) pi[a][b] = pi6[PI_IDX[a][b]];
+    return fneq_r(i, pi, u);
+}
+
+double or_fpost(int i, const double *m, const double *g, double omega)
+{
+    lattice_init();
+    return fpost_r(i, m, g, omega);
+}
+
+void or_moments(const double *f, double *m)
+{
+    lattice_init();
+    moments_r(f, m);
+}
+
+int or_node_kind(const or_grid *G, long n) { return node_kind(G, n); }
+
+void or_ghost_fill(const or_grid *G, double *st, long t)
+{
+    lattice_init();
+    ghost_fill_r(G, st, t);
+}
+
+/* One step: out <- update(in) at level t -> t+1 (ghosts of out refilled). */
+void or_step(const or_grid *G, const double *in, double *out, const double *gf, long t)
+{
+    lattice_init();
+    step_r(G, in, out, gf, t);
+}
+
+/* Storage rounding emulation: the stored quantities (rho - 1) s0, u s1 and
+ * Pi s2 are rounded to binary16 (kind 1) or bfloat16 (kind 2).             */
+void or_round_storage(const or_grid *G, double *st, int kind, const double *scale)
+{
+    const long N = (long)G->nx * G->ny * G->nz;
+    double (*rnd)(double) = kind == 1 ? or_round_fp16 : or_round_bf16;
+    for (long n = 0; n < N; n++) {
+        st[n] = 1.0 + rnd((st[n] - 1.0) * scale[0]) / scale[0];
+        for (int q = 1; q < 4; q++) st[q * N + n] = rnd(st[q * N + n] * scale[1]) / scale[1];
+        for (int q = 4; q < 10; q++) st[q * N + n] = rnd(st[q * N + n] * scale[2]) / scale[2];
+    }
+}
+
+/* nsteps steps in place starting at level t0; storage 0 = exact FP64,
+ * 1/2 = round the stored fields after every step (see or_round_storage).   */
+int or_run(const or_grid *G, double *st, const double *gf, long t0, int nsteps, int storage,
+           const double *scale)
+{
+    lattice_init();
+    const long N = (long)G->nx * G->ny * G->nz;
+    double *tmp = (double *)malloc(sizeof(double) * 10 * N);
+    if (!tmp) return -1;
+    for (int s = 0; s < nsteps; s++) {
+        step_r(G, st, tmp, gf, t0 + s);
+        if (storage) or_round_storage(G, tmp, storage, scale);
+        memcpy(st, tmp, sizeof(double) * 10 * N);
+    }
+    free(tmp);
+    return 0;
+}
+
+/* Single-step update at selected fluid nodes only (for sampled checks of
+ * large grids): out[q*nidx + k] = new moment q of node idx[k].             */
+void or_update_nodes(const or_grid *G, const double *in, const double *gf, const long *idx, long nidx,
+                     double *out)
+{
+    lattice_init();
+#pragma omp parallel for schedule(static)
+    for (long k = 0; k < nidx; k++) {
+        double f[NQ], m[10];
+        gather_r(G, in, gf, idx[k], f);
+        moments_r(f, m);
+        for (int q = 0; q < 10; q++) out[q * nidx + k] = m[q];
+    }
+}
+
+/* FP64 sums over fluid nodes: mass, momentum (3), kinetic energy 1/2 rho u^2.
+ * Returns the number of non-finite entries met.                             */
+long or_reduce(const or_grid *G, const double *st, double *out)
+{
+    const long N = (long)G->nx * G->ny * G->nz;
+    long bad = 0;
+    for (int k = 0; k < 5; k++) out[k] = 0.0;
+    for (long n = 0; n < N; n++) {
+        if (node_kind(G, n) != NODE_FLUID) continue;
+        double rho = st[n], u[3] = {st[N + n], st[2 * N + n], st[3 * N + n]};
+        for (int q = 0; q < 10; q++)
+            if (!isfinite(st[q * N + n])) bad++;
+        out[0] += rho;
+        for (int a = 0; a < 3; a++) out[1 + a] += rho * u[a];
+        out[4] += 0.5 * rho * (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+    }
+    return bad;
+}
+
+uint64_t or_splitmix64(uint64_t seed, uint64_t k) { return splitmix64_at(seed, k); }
+double or_inlet_xi(uint64_t seed, long t, long n, long N, int a) { return inlet_xi(seed, t, n, N, a); }
+
+/* ------------------------------------------------------------------ */
+/* Tangent and adjoint of one step (fluid nodes; periodic axes and walls;
+ * ghost layers are not differentiated).                                   */
+
+/* Tangent (Jacobian-vector product) of one step by the complex step:
+ * dout = d step(st, gf) [dst, dgf].                                        */
+int or_jvp_step(const or_grid *G, const double *st, const double *gf, const double *dst, const double *dgf,
+                long t, double *dout)
+{
+    lattice_init();
+    const long N = (long)G->nx * G->ny * G->nz;
+    double complex *a = (double complex *)malloc(sizeof(double complex) * 10 * N);
+    double complex *b = (double complex *)malloc(sizeof(double complex) * 10 * N);
+    double complex *g = (double complex *)malloc(sizeof(double complex) * 3 * N);
+    if (!a || !b || !g) return -1;
+    for (long k = 0; k < 10 * N; k++) a[k] = st[k] + I * CSTEP * dst[k];
+    for (long k = 0; k < 3 * N; k++) {
+        double g0 = gf ? gf[k] : G->force[k / N];
+        double dg = dgf ? dgf[k] : 0.0;
+        g[k] = g0 + I * CSTEP * dg;
+    }
+    step_c(G, a, b, g, t);
+    for (long k = 0; k < 10 * N; k++) dout[k] = cimag(b[k]) / CSTEP;
+    free(a);
+    free(b);
+    free(g);
+    return 0;
+}
+
+/* Adjoint of the moment map at fluid node x: lf[i] = sum_q lam_q dM'_q/df_i,
+ * with the populations f arriving at x rebuilt from st.                     */
+static void adjoint_populations(const or_grid *G, const double *st, const double *gf, const double *lam,
+                                long x, double lf[NQ])
+{
+    const long N = (long)G->nx * G->ny * G->nz;
+    double f[NQ];
+    gather_r(G, st, gf, x, f);
+    for (int i = 0; i < NQ; i++) {
+        double complex fc[NQ], mc[10];
+        for (int k = 0; k < NQ; k++) fc[k] = f[k];
+        fc[i] += I * CSTEP;
+        moments_c(fc, mc);
+        double s = 0.0;
+        for (int q = 0; q < 10; q++) s += lam[q * N + x] * cimag(mc[q]) / CSTEP;
+        lf[i] = s;
+    }
+}
+
+/* Accumulate J^T lf into lm[10] (moments) and lg[3] (force) for the
+ * population k emitted by node s: J = d fpost_k / d (M_s, g_s).            */
+static void adjoint_emit(const or_grid *G, const double *st, const double *gf, long s, int k, double lf,
+                         double lm[10], double lg[3])
+{
+    const long N = (long)G->nx * G->ny * G->nz;
+    double omega = 1.0 / G->tau;
+    for (int p = 0; p < 13; p++) {
+        double complex m[10], g[3];
+        for (int q = 0; q < 10; q++) m[q] = st[q * N + s];
+        for (int a = 0; a < 3; a++) g[a] = gf ? gf[a * N + s] : G->force[a];
+        if (p < 10)
+            m[p] += I * CSTEP;
+        else
+            g[p - 10] += I * CSTEP;
+        double d = cimag(fpost_c(k, m, g, omega)) / CSTEP;
+        if (p < 10)
+            lm[p] += d * lf;
+        else
+            lg[p - 10] += d * lf;
+    }
+}
+
+/* Reverse-mode sensitivity at node y (gather from the downstream nodes):
+ * lam_t(y) = sum over populations emitted by y of J^T lam_f, where y emits
+ * population i to y + c_i, and, for each direction whose upstream node is
+ * solid, its own bounced-back population OPP[i] to itself.                  */
+static int adjoint_node(const or_grid *G, const double *st, const double *gf, const double *lam1,
+                        const double *lf_all, long y, double lm[10], double lg[3])
+{
+    for (int q = 0; q < 10; q++) lm[q] = 0.0;
+    for (int a = 0; a < 3; a++) lg[a] = 0.0;
+    if (node_kind(G, y) != NODE_FLUID) return 0;
+    int xy[3];
+    node_coords(G, y, xy);
+    for (int i = 0; i < NQ; i++) {
+        int xd[3], ok = 1;
+        for (int d = 0; d < 3; d++) {
+            int n = dim(G, d);
+            xd[d] = xy[d] + OC[i][d];
+            if (G->face[2 * d] == FACE_PERIODIC) xd[d] = ((xd[d] % n) + n) % n;
+            if (xd[d] < 0 || xd[d] >= n) ok = 0;
+        }
+        if (ok && node_kind_xyz(G, xd) == NODE_FLUID) {
+            long x = node_index(G, xd);
+            double lf[NQ];
+            if (lf_all)
+                memcpy(lf, lf_all + (size_t)x * NQ, sizeof lf);
+            else
+                adjoint_populations(G, st, gf, lam1, x, lf);
+            adjoint_emit(G, st, gf, y, i, lf[i], lm, lg);
+        }
+        if (upstream(G, xy, i) == -1) { /* bounce-back: y feeds itself */
+            double lf[NQ];
+            if (lf_all)
+                memcpy(lf, lf_all + (size_t)y * NQ, sizeof lf);
+            else
+                adjoint_populations(G, st, gf, lam1, y, lf);
+            adjoint_emit(G, st, gf, y, OPP[i], lf[i], lm, lg);
+        }
+    }
+    return 0;
+}
+
+/* Full-grid adjoint of one step from level t: lam_t = J_M^T lam_{t+1} and
+ * dg += J_g^T lam_{t+1} (dg may be NULL).  Ghost layers are unsupported.    */
+int or_adjoint_step(const or_grid *G, const double *st, const double *gf, const double *lam1, double *lam0,
+                    double *dg)
+{
+    lattice_init();
+    if (grid_has_ghosts(G)) return -1;
+    const long N = (long)G->nx * G->ny * G->nz;
+    double *lf_all = (double *)calloc((size_t)N * NQ, sizeof(double));
+    if (!lf_all) return -1;
+#pragma omp parallel for schedule(static)
+    for (long x = 0; x < N; x++)
+        if (node_kind(G, x) == NODE_FLUID) adjoint_populations(G, st, gf, lam1, x, lf_all + (size_t)x * NQ);
+#pragma omp parallel for schedule(static)
+    for (long y = 0; y < N; y++) {
+        double lm[10], lg[3];
+        adjoint_node(G, st, gf, lam1, lf_all, y, lm, lg);
+        for (int q = 0; q < 10; q++) lam0[q * N + y] = lm[q];
+        if (dg)
+            for (int a = 0; a < 3; a++) dg[a * N + y] += lg[a];
+    }
+    free(lf_all);
+    return 0;
+}
+
+/* Adjoint of one step at selected nodes only: lam_out[q*nidx+k], dg_out[a*nidx+k]. */
+int or_adjoint_nodes(const or_grid *G, const double *st, const double *gf, const double *lam1, const long *idx,
+                     long nidx, double *lam_out, double *dg_out)
+{
+    lattice_init();
+    if (grid_has_ghosts(G)) return -1;
+#pragma omp parallel for schedule(dynamic, 4)
+    for (long k = 0; k < nidx; k++) {
+        double lm[10], lg[3];
+        adjoint_node(G, st, gf, lam1, NULL, idx[k], lm, lg);
+        for (int q = 0; q < 10; q++) lam_out[q * nidx + k] = lm[q];
+        for (int a = 0; a < 3; a++) dg_out[a * nidx + k] = lg[a];
+    }
+    return 0;
+}
+
+/* Kinetic-energy objective L = 1/2 sum_fluid rho |u|^2 and its gradient
+ * with respect to the stored moments (rho, u, Pi).                          */
+double or_ke_seed(const or_grid *G, const double *st, double *lam)
+{
+    const long N = (long)G->nx * G->ny * G->nz;
+    double L = 0.0;
+    memset(lam, 0, sizeof(double) * 10 * N);
+    for (long n = 0; n < N; n++) {
+        if (node_kind(G, n) != NODE_FLUID) continue;
+        double rho = st[n], u2 = 0.0;
+        for (int a = 0; a < 3; a++) u2 += st[(1 + a) * N + n] * st[(1 + a) * N + n];
+        L += 0.5 * rho * u2;
+        lam[n] = 0.5 * u2;
+        for (int a = 0; a < 3; a++) lam[(1 + a) * N + n] = rho * st[(1 + a) * N + n];
+    }
+    return L;
+}
+
+/* Gradient of L(state after nsteps) with respect to the initial state and the
+ * force field, by storing every level and sweeping the adjoint backwards.
+ * lam0 (10N) receives dL/dM_0; dg (3N, may be NULL) receives dL/dg.          */
+int or_rollout_grad(const or_grid *G, const double *st0, const double *gf, long t0, int nsteps, double *loss,
+                    double *lam0, double *dg)
+{
+    lattice_init();
+    if (grid_has_ghosts(G)) return -1;
+    const long N = (long)G->nx * G->ny * G->nz;
+    double *traj = (double *)malloc(sizeof(double) * 10 * N * (size_t)(nsteps + 1));
+    double *lam = (double *)malloc(sizeof(double) * 10 * N);
+    double *tmp = (double *)malloc(sizeof(double) * 10 * N);
+    if (!traj || !lam || !tmp) return -1;
+    memcpy(traj, st0, sizeof(double) * 10 * N);
+    for (int s = 0; s < nsteps; s++)
+        step_r(G, traj + (size_t)s * 10 * N, traj + (size_t)(s + 1) * 10 * N, gf, t0 + s);
+    *loss = or_ke_seed(G, traj + (size_t)nsteps * 10 * N, lam);
+    if (dg) memset(dg, 0, sizeof(double) * 3 * N);
+    for (int s = nsteps - 1; s >= 0; s--) {
+        or_adjoint_step(G, traj + (size_t)s * 10 * N, gf, lam, tmp, dg);
+        memcpy(lam, tmp, sizeof(double) * 10 * N);
+    }
+    memcpy(lam0, lam, sizeof(double) * 10 * N);
+    free(traj);
+    free(lam);
+    free(tmp);
+    return 0;
+}

@@ -1,0 +1,164 @@
+"""Pins of the oracle's ghost layers (Section 2.3), inlet random numbers,
+storage rounding, and its tangent and adjoint.
+
+- The ghost rule is checked value by value against its definition; the
+  random stream against the published SplitMix64 outputs.
+- Binary16 / bfloat16 rounding is checked against numpy's and torch's
+  conversions (library routines) on inputs where they are exact references.
+- The adjoint is pinned twice: by the dot-product identity against the
+  complex-step tangent of the whole step, and by central finite differences
+  in FP64 of the kinetic-energy loss through a short rollout.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def test_splitmix64_published_outputs(oracle):
+    rows = [ln.split() for ln in open(os.path.join(HERE, "golden", "splitmix64_seed0.txt"))
+            if ln.strip() and not ln.startswith("#")]
+    for k, hexval in rows:
+        assert oracle.splitmix64(0, int(k)) == int(hexval, 16)
+
+
+def test_inlet_variate_bits(oracle):
+    """xi = 2 * (top 24 bits of output k) / 2^24 - 1, k = 1 + 3 (t N + n) + a."""
+    seed, N = 987654321, 1000
+    for (t, n, a) in [(0, 0, 0), (3, 17, 2), (1999, 999, 1)]:
+        k = 1 + 3 * (t * N + n) + a
+        h = oracle.splitmix64(seed, k)
+        assert oracle.inlet_xi(seed, t, n, N, a) == (h >> 40) / 2.0 ** 24 * 2 - 1
+    xs = np.array([oracle.inlet_xi(seed, 5, n, N, 0) for n in range(4000)])
+    assert xs.min() >= -1 and xs.max() < 1 and abs(xs.mean()) < 0.05
+
+
+def test_ghost_fill_rule(oracle):
+    case = W.jet_case(nx=9, ny=12, nz=11, D=4.0)
+    G = oracle.make_grid(case.nx, case.ny, case.nz, case.tau, faces=case.faces, inlet_u=case.inlet_u,
+                         inlet_center=case.inlet_center, inlet_radius=case.inlet_radius,
+                         inlet_noise=case.inlet_noise, seed=case.seed)
+    st = W.random_state(G.shape, seed=21)
+    t = 7
+    out = oracle.ghost_fill(G, st, t)
+    kinds = oracle.node_kinds(G)
+    nz, ny, nx = G.shape
+    N = G.n
+    U = np.array(case.inlet_u)
+    amp = case.inlet_noise * np.linalg.norm(U)
+    n_inlet = 0
+    for z in range(nz):
+        for y in range(ny):
+            for x in range(nx):
+                if kinds[z, y, x] == 0:
+                    assert np.array_equal(out[:, z, y, x], st[:, z, y, x])
+                    continue
+                xf, yf, zf = min(max(x, 1), nx - 2), min(max(y, 1), ny - 2), min(max(z, 1), nz - 2)
+                src = st[:, zf, yf, xf]
+                r2 = (y - case.inlet_center[0]) ** 2 + (z - case.inlet_center[1]) ** 2
+                if x == 0 and r2 <= case.inlet_radius ** 2:
+                    n_inlet += 1
+                    n = x + nx * (y + ny * z)
+                    ub = U + amp * np.array([oracle.inlet_xi(case.seed, t, n, N, a) for a in range(3)])
+                    assert out[0, z, y, x] == src[0]
+                    assert np.array_equal(out[4:, z, y, x], src[4:])
+                    assert np.allclose(out[1:4, z, y, x], ub, rtol=0, atol=1e-17)
+                    assert np.all(np.abs(out[1:4, z, y, x] - U) <= amp)
+                else:
+                    assert np.array_equal(out[:, z, y, x], src)
+    # lattice points of the disc (y - 5.5)^2 + (z - 5)^2 <= 4: dy = +-0.5, +-1.5 with |dz| <= 1
+    assert n_inlet == 12
+
+
+def test_ghost_layers_do_not_leak_mass_when_uniform(oracle):
+    """A uniform rest state with zero-gradient ghosts everywhere is a fixed point."""
+    G = oracle.make_grid(6, 7, 5, 0.51, faces=(3,) * 6)
+    st = oracle.ghost_fill(G, W.rest_state(G.shape), 0)
+    out = oracle.run(G, st, 5)
+    assert np.abs(out - st).max() < 1e-15
+
+
+def test_fp16_rounding_matches_numpy(oracle):
+    rng = np.random.default_rng(22)
+    xs = np.concatenate([rng.standard_normal(3000) * 10.0 ** rng.integers(-9, 5, 3000),
+                         [0.0, 6.1e-5, 5.96e-8, 2.98e-8, 65504.0, 65519.0, 65520.0, -1e-9]])
+    for x in xs:
+        assert oracle.round_fp16(x) == float(np.float64(x).astype(np.float16)), x
+
+
+def test_bf16_rounding_matches_torch(oracle):
+    torch = pytest.importorskip("torch")
+    rng = np.random.default_rng(23)
+    xs = (rng.standard_normal(3000) * 10.0 ** rng.integers(-30, 30, 3000)).astype(np.float32)
+    ref = torch.from_numpy(xs).to(torch.bfloat16).to(torch.float64).numpy()
+    got = np.array([oracle.round_bf16(float(x)) for x in xs])
+    assert np.array_equal(got, ref)
+
+
+def test_storage_rounding_emulation(oracle):
+    G = oracle.make_grid(3, 3, 3, 0.7)
+    st = W.random_state(G.shape, seed=24)
+    sc = (2.0 ** 10, 2.0 ** 12, 2.0 ** 16)
+    r = oracle.round_storage(G, st, 1, sc)
+    assert np.array_equal(((r[0] - 1) * sc[0]).astype(np.float16).astype(np.float64), (r[0] - 1) * sc[0])
+    assert np.array_equal((r[4:] * sc[2]).astype(np.float16).astype(np.float64), r[4:] * sc[2])
+    assert np.abs(r[1:4] - st[1:4]).max() <= 2.0 ** -11 * 0.03
+
+
+@pytest.mark.parametrize("faces", [(0,) * 6, (0, 0, 1, 1, 0, 0)])
+def test_adjoint_dot_product_identity(oracle, faces):
+    """<lam, J v> = <J^T lam, v> with J v from the complex-step tangent."""
+    G = oracle.make_grid(5, 6, 4, 0.61, faces=faces)
+    st = W.random_state(G.shape, seed=25, u_amp=0.05, pi_amp=2e-3)
+    g = W.random_force(G.shape, seed=26, amp=1e-4)
+    rng = np.random.default_rng(27)
+    v = rng.standard_normal(st.shape)
+    dg = rng.standard_normal(g.shape)
+    lam1 = rng.standard_normal(st.shape)
+    kinds = oracle.node_kinds(G)
+    lam1[:, kinds != 0] = 0.0  # the loss only sees fluid nodes
+    jv = oracle.jvp_step(G, st, v, g, dg)
+    lam0, gg = oracle.adjoint_step(G, st, lam1, g)
+    lhs = (lam1 * jv).sum()
+    rhs = (lam0 * v).sum() + (gg * dg).sum()
+    assert lhs == pytest.approx(rhs, rel=1e-12)
+
+
+def test_adjoint_nodes_match_full_adjoint(oracle):
+    G = oracle.make_grid(4, 6, 5, 0.7, faces=(0, 0, 1, 1, 0, 0))
+    st = W.random_state(G.shape, seed=28)
+    lam1 = np.random.default_rng(29).standard_normal(st.shape)
+    lam0, dg = oracle.adjoint_step(G, st, lam1)
+    idx = np.arange(0, G.n, 7)
+    lam_s, dg_s = oracle.adjoint_nodes(G, st, lam1, idx)
+    assert np.allclose(lam_s, lam0.reshape(10, -1)[:, idx], rtol=1e-13, atol=1e-14)
+    assert np.allclose(dg_s, dg.reshape(3, -1)[:, idx], rtol=1e-13, atol=1e-14)
+
+
+def test_rollout_gradient_matches_central_differences(oracle):
+    """FP64 central differences (h = 1e-4 relative) of L = 1/2 sum rho |u|^2
+    after 8 steps, along random directions of g and of the initial velocity."""
+    case = W.adjoint_case(n=6, steps=8)
+    G = oracle.make_grid(case.nx, case.ny, case.nz, case.tau)
+    st0, g = W.adjoint_inputs(case)
+    g = g * 1e3  # a force large enough that its gradient is not round-off
+    L, lam0, dg = oracle.rollout_grad(G, st0, case.steps, g)
+    rng = np.random.default_rng(30)
+
+    def loss(s, gf):
+        return oracle.ke_seed(G, oracle.run(G, s, case.steps, gf))[0]
+
+    for _ in range(2):
+        d = rng.standard_normal(g.shape)
+        h = 1e-4 * np.abs(g).max()
+        fd = (loss(st0, g + h * d) - loss(st0, g - h * d)) / (2 * h)
+        assert (dg * d).sum() == pytest.approx(fd, rel=1e-6)
+        du = np.zeros_like(st0)
+        du[1:4] = rng.standard_normal((3,) + G.shape)
+        h = 1e-4 * np.abs(st0[1:4]).max()
+        fd = (loss(st0 + h * du, g) - loss(st0 - h * du, g)) / (2 * h)
+        assert (lam0 * du).sum() == pytest.approx(fd, rel=1e-6)
