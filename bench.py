@@ -1,0 +1,259 @@
+"""Benchmark of the moment-only high-order TSLB update on one MI355X.
+
+Workload (the timed `value`): the channel-shaped flow, D3Q27, 384 x 192 x 192
+nodes (x, z periodic; bounce-back walls at y = 0 and y = ny - 1), friction
+Reynolds number 180 forcing, tau = 0.5045, FP32 moments, seeded synthetic
+initial state (parabolic profile + 5 % uniform perturbations).  One step is
+one full update of every node (the paper's lattice-update count, Section 4).
+
+Printed: ONE JSON line with MLUPS, the HBM roofline of the update kernel
+(algorithmic bytes per launch / measured average launch time), the FP64 CPU
+oracle timed on the host cores on a bounded sample of the same workload, and
+side measurements named by the metric: FP16/BF16-moment storage on the
+512 x 256 x 256 channel, and the adjoint-to-forward time ratio on the
+64^3 forced periodic box with checkpoints every 20 steps.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+BYTES_PER_FIELD = {0: 4, 1: 2, 2: 2}
+
+
+def _source_hash():
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_2401_17074_amd", "csrc")
+    for name in sorted(os.listdir(d)):
+        if name.endswith((".hip", ".h")):
+            h.update(open(os.path.join(d, name), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def _fluid_nodes(case):
+    n = [case.nx, case.ny, case.nz]
+    for d in range(3):
+        lo, hi = case.faces[2 * d], case.faces[2 * d + 1]
+        n[d] -= (lo != 0) + (hi != 0)
+    return n[0] * n[1] * n[2]
+
+
+def algorithmic_bytes(case, storage):
+    """Bytes one update launch must move: read the ten stored fields of
+    every node once, write the ten fields of every fluid node once."""
+    b = BYTES_PER_FIELD[storage]
+    return 10 * b * case.nodes + 10 * b * _fluid_nodes(case)
+
+
+def time_steps(solver, steps, warmup):
+    import torch
+    solver.step(warmup)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record()
+    solver.step(steps)
+    e1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return e0.elapsed_time(e1), wall
+
+
+def _solver(case, storage=0, kernel=0):
+    import numpy as np
+    from paper_2401_17074_amd import Solver
+    f32 = lambda v: float(np.float32(v))  # noqa: E731
+    return Solver(case.nx, case.ny, case.nz, f32(case.tau), force=[f32(v) for v in case.force], faces=case.faces,
+                  storage=storage, inlet_u=case.inlet_u, inlet_center=case.inlet_center,
+                  inlet_radius=case.inlet_radius, inlet_noise=case.inlet_noise, seed=case.seed, kernel=kernel)
+
+
+def _device_state(st64):
+    import numpy as np
+    dev = st64.astype(np.float32)
+    dev[0] = (st64[0] - 1.0).astype(np.float32)
+    return dev
+
+
+def measure_storage_variants(steps, warmup, kernel):
+    import workloads as W
+    case = W.channel_case(nx=512, ny=256, nz=256)
+    st = _device_state(W.channel_state(case))
+    out = {}
+    for storage, name in ((0, "fp32"), (1, "fp16"), (2, "bf16")):
+        s = _solver(case, storage, kernel)
+        s.set_state(st)
+        ms, _ = time_steps(s, steps, warmup)
+        s.close()
+        mlups = case.nodes * steps / (ms * 1e-3) / 1e6
+        gbs = algorithmic_bytes(case, storage) * steps / (ms * 1e-3) / 1e9
+        out[name] = {"mlups": round(mlups, 1), "hbm_gbs": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
+    return {"workload": case.name, "steps": steps, **out}
+
+
+def measure_adjoint(kernel):
+    import numpy as np
+    import torch
+    import workloads as W
+    from paper_2401_17074_amd import capi as C
+    case = W.adjoint_case()
+    st, g = W.adjoint_inputs(case)
+    s = _solver(case, 0, kernel)
+    s.set_force_field(g.astype(np.float32))
+    s.set_state(_device_state(st))
+    nsteps, every = case.steps, case.extra["ckpt"]
+    ws = torch.empty(C.tslb_rollout_workspace_bytes(s.h, nsteps, every), dtype=torch.uint8, device="cuda")
+    # warm up both directions once
+    C.tslb_rollout_forward(s.h, nsteps, every, ws)
+    lam = s.adjoint_seed(s.save_raw())
+    dg = torch.zeros((3,) + case.shape, dtype=torch.float32, device="cuda")
+    C.tslb_rollout_backward(s.h, nsteps, every, ws, lam, dg)
+    s.set_state(_device_state(st))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    C.tslb_rollout_forward(s.h, nsteps, every, ws)
+    torch.cuda.synchronize()
+    t_fwd = time.perf_counter() - t0
+    lam = s.adjoint_seed(s.save_raw())
+    dg.zero_()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    C.tslb_rollout_backward(s.h, nsteps, every, ws, lam, dg)
+    torch.cuda.synchronize()
+    t_bwd = time.perf_counter() - t0
+    # kernel-only: one adjoint step vs one forward step, event timed
+    raw0 = s.save_raw()
+    s.step(1)
+    raw1 = s.save_raw()
+    lam_out = torch.empty_like(lam)
+    reps = 50
+    e = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    e[0].record()
+    for _ in range(reps):
+        C.tslb_adjoint_step(s.h, raw0, raw1, lam, lam_out, dg)
+    e[1].record()
+    e[2].record()
+    s.step(reps)
+    e[3].record()
+    torch.cuda.synchronize()
+    s.close()
+    k_adj = e[0].elapsed_time(e[1]) / reps
+    k_fwd = e[2].elapsed_time(e[3]) / reps
+    return {"workload": case.name, "steps": nsteps, "checkpoint_every": every,
+            "forward_ms_per_step": round(t_fwd * 1e3 / nsteps, 4),
+            "backward_ms_per_step": round(t_bwd * 1e3 / nsteps, 4),
+            "adjoint_over_forward": round(t_bwd / t_fwd, 3),
+            "adjoint_kernel_over_update_kernel": round(k_adj / k_fwd, 3)}
+
+
+def cpu_baseline(case, st64, seconds_budget=15.0):
+    """The FP64 oracle as it stands, on the host cores: single-step updates of a
+    contiguous block of z-planes of the same channel state."""
+    import numpy as np
+    import oracle
+    G = oracle.make_grid(case.nx, case.ny, case.nz, case.tau, faces=case.faces, force=case.force)
+    plane = case.nx * case.ny
+    kinds = oracle.node_kinds(G).reshape(-1)
+    # calibrate on one plane, then size the sample to the time budget
+    idx = np.arange(plane, 2 * plane)
+    idx = idx[kinds[idx] == 0]
+    t0 = time.perf_counter()
+    oracle.update_nodes(G, st64, idx)
+    dt = time.perf_counter() - t0
+    nplanes = int(max(1, min(case.nz - 2, seconds_budget / max(dt, 1e-6))))
+    idx = np.arange(plane, (1 + nplanes) * plane)
+    idx = idx[kinds[idx] == 0]
+    t0 = time.perf_counter()
+    oracle.update_nodes(G, st64, idx)
+    dt = time.perf_counter() - t0
+    return {"value": round(idx.size / dt / 1e6, 4), "unit": "MLUPS", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": "one FP64 update of %d fluid nodes (%d z-planes) of the %s initial state, %.1f s"
+                      % (idx.size, nplanes, case.name, dt)}
+
+
+def load_traffic(kernel_name, case_name, storage):
+    """HBM bytes per launch from a committed rocprofv3 counter summary, only
+    if it was taken on the current kernel sources."""
+    path = os.path.join(ROOT, "profiles", "pmc_%s_%s.json" % (kernel_name, case_name))
+    if not os.path.exists(path):
+        return None
+    try:
+        rec = json.load(open(path))
+    except ValueError:
+        return None
+    if rec.get("source_hash") != _source_hash() or rec.get("storage") != storage:
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--kernel", type=int, default=0, help="0 tiled (default), 1 direct")
+    ap.add_argument("--quick", action="store_true", help="only the timed workload (for profiling)")
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build runs on a single MI355X and has no multi-GPU path "
+              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import workloads as W
+    torch.cuda.set_device(0)
+
+    case = W.channel_case(steps=args.steps)
+    st64 = W.channel_state(case)
+    s = _solver(case, 0, args.kernel)
+    s.set_state(_device_state(st64))
+    ms, wall = time_steps(s, args.steps, args.warmup)
+    _, rc = s.reduce(check=False)
+    s.close()
+    mlups = case.nodes * args.steps / (ms * 1e-3) / 1e6
+    kname = "update_tiled" if args.kernel == 0 else "update_direct"
+    per_launch_s = ms * 1e-3 / args.steps
+    algo = algorithmic_bytes(case, 0)
+    achieved = algo / per_launch_s / 1e9
+    rec = {
+        "metric": "MLUPS and % of HBM roofline (FP32 vs FP16-moment); adjoint step time / forward",
+        "value": round(mlups, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms / args.steps, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": case.name, "nodes": case.nodes, "lattice": "D3Q27", "tau": case.tau,
+                   "storage": "fp32", "boundaries": "x,z periodic; bounce-back walls y=0,ny-1",
+                   "kernel": kname, "stable": rc == 0},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": load_traffic(kname, case.name, 0),
+                     "algorithmic_bytes_per_launch": algo, "avg_launch_ms": round(per_launch_s * 1e3, 5)},
+        "wall_s": round(wall, 3),
+    }
+    if not args.quick:
+        rec["storage_variants"] = measure_storage_variants(200, 10, args.kernel)
+        rec["adjoint"] = measure_adjoint(args.kernel)
+        if not args.no_cpu:
+            rec["cpu_baseline"] = cpu_baseline(case, st64)
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

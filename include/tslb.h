@@ -1,0 +1,186 @@
+/*
+ * tslb.h - C ABI of the MI355X (gfx950) moment-only, high-order thread-safe
+ * lattice Boltzmann library.
+ *
+ * Method: Montessori et al., "High-order thread-safe lattice Boltzmann model
+ * for HPC turbulent flow simulations", arXiv:2401.17074.  Each time step,
+ * every fluid node x pulls the moments (rho, u, Pi^neq) of its 27 D3Q27
+ * upstream neighbours x - c_i, rebuilds each population as the third-order
+ * Hermite equilibrium (Section 2.2, Eq. (eqts)) plus (1 - omega) times the
+ * non-equilibrium part rebuilt by the Hermite recursion (Eq. (noneqts)), adds
+ * the local body-force term (Section 3.1), and sums the new moments (the full
+ * update of Section 2.2).  Only the ten moments are stored (Section 2.2, the
+ * storage remark), double-buffered, structure-of-arrays.
+ *
+ * Conventions shared by every call
+ *  - Grid: nx * ny * nz nodes, node index n = x + nx * (y + ny * z).
+ *  - Field arrays are structure-of-arrays, x fastest: u is 3N floats
+ *    (u_x block, u_y block, u_z block); Pi^neq is 6N floats ordered
+ *    xx, yy, zz, xy, xz, yz; a force field is 3N floats like u.
+ *  - Node classes follow from coordinates and the face kinds: a node on a
+ *    TSLB_WALL face layer is solid (half-way bounce-back, walls win); a node
+ *    on a TSLB_INLET / TSLB_OUTLET face layer is a ghost whose moments are
+ *    refilled from the nearest interior node after every step (Section 2.3,
+ *    Eq. (neq_final)); every other node is fluid and is updated.
+ *  - Pointers are borrowed for the duration of the call; the handle owns its
+ *    state buffers.  `stream` is a hipStream_t passed as void* (NULL = the
+ *    default stream).  Calls are asynchronous on that stream unless they say
+ *    otherwise.
+ *  - Every call returns TSLB_OK (0) or a negative TSLB_E_* code; the message
+ *    of the last failure on the calling thread is tslb_last_error().  No C++
+ *    exception crosses this interface.
+ */
+#ifndef TSLB_H
+#define TSLB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct tslb_ctx *tslb_handle; /* opaque, owned by the library */
+
+enum { TSLB_D3Q27 = 27 };                                   /* the only lattice (Section 2.1) */
+enum { TSLB_FP32 = 0, TSLB_FP16 = 1, TSLB_BF16 = 2 };       /* moment storage; compute is FP32 */
+enum { TSLB_PERIODIC = 0, TSLB_WALL = 1, TSLB_INLET = 2, TSLB_OUTLET = 3 }; /* face kinds */
+enum { TSLB_DEVICE = 1, TSLB_RHO_DEVIATION = 2 };           /* set/get flags */
+enum { TSLB_OBJ_KINETIC_ENERGY = 0 };                       /* adjoint objectives */
+enum {
+    TSLB_OK = 0,
+    TSLB_E_INVALID = -1,     /* bad argument (tau <= 1/2, dims, unpaired periodic faces, ...) */
+    TSLB_E_UNSUPPORTED = -2, /* valid request this library does not provide */
+    TSLB_E_NOMEM = -3,       /* device allocation failed */
+    TSLB_E_HIP = -4,         /* a HIP runtime call failed */
+    TSLB_E_UNSTABLE = -5     /* tslb_reduce met a NaN or Inf */
+};
+
+/* Boundary and storage description.
+ *  face[6]         kinds of the faces -x, +x, -y, +y, -z, +z.  PERIODIC faces
+ *                  come in pairs; a non-periodic axis needs at least 3 nodes.
+ *  inlet_*         for TSLB_INLET faces: nodes of the face layer inside the
+ *                  disc |(t1, t2) - inlet_center| <= inlet_radius (t1 < t2 are
+ *                  the two transverse axes in x, y, z order) get
+ *                  u = inlet_u + inlet_noise * |inlet_u| * xi, with xi uniform
+ *                  in [-1, 1) per component, drawn from the SplitMix64 stream
+ *                  of `seed` at position k = 1 + 3 (t N + n) + component for
+ *                  level t and node n; rho and Pi^neq come from the interior
+ *                  neighbour.  The rest of an inlet face behaves as an outlet
+ *                  (all ten moments copied from the interior neighbour).
+ *  storage         TSLB_FP32 / TSLB_FP16 / TSLB_BF16 for the stored moments.
+ *  scale[3]        power-of-two factors applied before rounding to 16 bits:
+ *                  stored = (rho - 1) * scale[0], u * scale[1], Pi * scale[2].
+ *                  0 selects the default for the storage kind (1 for FP32 and
+ *                  BF16; 2^12, 2^12, 2^16 for FP16, which keeps |rho - 1| and
+ *                  |u| below 16 and |Pi| below 1 clear of overflow and small
+ *                  values clear of subnormals).  Ignored for FP32.            */
+typedef struct {
+    int face[6];
+    float inlet_u[3];
+    float inlet_center[2];
+    float inlet_radius;
+    float inlet_noise;
+    uint64_t seed;
+    int storage;
+    float scale[3];
+} tslb_bc;
+
+/* Create a solver on an nx*ny*nz grid (Section 2.2 update, D3Q27 only).
+ * tau: relaxation time, nu = (tau - 1/2) / 3 (Section 2), must exceed 1/2.
+ * force: uniform body acceleration g (Section 3.1 forcing), may be NULL (0).
+ * bc: may be NULL (all faces periodic, FP32 storage).
+ * Allocates two state buffers on the current HIP device, sets the rest
+ * state rho = 1, u = 0, Pi^neq = 0 at level t = 0, and synchronises.
+ * Errors: TSLB_E_INVALID, TSLB_E_UNSUPPORTED (lattice != 27), TSLB_E_NOMEM. */
+int tslb_create(int nx, int ny, int nz, int lattice, float tau, const float force[3], const tslb_bc *bc,
+                tslb_handle *out);
+
+/* Free the buffers of h (synchronises the device first).  NULL is a no-op. */
+int tslb_destroy(tslb_handle h);
+
+/* Overwrite the state at the current level with rho (N), u (3N) and Pi^neq
+ * (6N, or NULL for zero).  flags: TSLB_DEVICE if the arrays are device
+ * memory (else host; the call then synchronises the stream),
+ * TSLB_RHO_DEVIATION if `rho` holds rho - 1.  Values are rounded to the
+ * storage format; ghost layers are then refilled from the interior (so input
+ * ghost values are ignored) and solid nodes are stored as given.           */
+int tslb_set_moments(tslb_handle h, const float *rho, const float *u, const float *pineq, int flags,
+                     void *stream);
+
+/* Read the current state (all nodes; ghosts hold their fill values, solid
+ * nodes what was last set).  Any output pointer may be NULL.  Same flags as
+ * tslb_set_moments; host reads synchronise the stream.                      */
+int tslb_get_moments(tslb_handle h, float *rho, float *u, float *pineq, int flags, void *stream);
+
+/* Use a per-node body-acceleration field g (3N floats, device memory,
+ * copied into the handle) instead of the uniform force; NULL returns to the
+ * uniform force given at creation.                                          */
+int tslb_set_force_field(tslb_handle h, const float *g, void *stream);
+
+/* Advance nsteps time steps (Section 2.2 update, then the ghost refill of
+ * Section 2.3 for the new level).  Asynchronous.  nsteps >= 0.               */
+int tslb_step(tslb_handle h, int nsteps, void *stream);
+
+/* Current level t (steps taken since creation, or the last tslb_set_time). */
+int64_t tslb_get_time(tslb_handle h);
+int tslb_set_time(tslb_handle h, int64_t t);
+
+/* FP64 sums over fluid nodes of the current state: out[0] = sum rho,
+ * out[1..3] = sum rho u, out[4] = 1/2 sum rho |u|^2 (conservation checks of
+ * Section 2).  Synchronises the stream.  Returns TSLB_E_UNSTABLE (with out
+ * still written) if any stored fluid moment is NaN or Inf.                   */
+int tslb_reduce(tslb_handle h, double out[5], void *stream);
+
+/* Raw state snapshots (for checkpoints and the adjoint): the state is
+ * tslb_state_bytes(h) bytes of device memory holding the ten stored fields
+ * in storage format, SoA, field 0 = (rho - 1) * scale[0].  dst/src are
+ * device pointers; asynchronous D2D copies.  Loading does not refill ghosts. */
+size_t tslb_state_bytes(tslb_handle h);
+int tslb_save_state(tslb_handle h, void *dst, void *stream);
+int tslb_load_state(tslb_handle h, const void *src, void *stream);
+
+/* Discrete adjoint (reverse-mode derivative) of one update step, the
+ * transpose of the Section 2.2 update linearised at state_t:
+ *   lam_t    = (dM_{t+1}/dM_t)^T lam_t1
+ *   dg_accum += (dM_{t+1}/dg)^T lam_t1   (per-node force field; may be NULL)
+ * state_t, state_t1: raw snapshots (tslb_save_state format) of levels t and
+ * t+1 = step(state_t).  lam_t1, lam_t: 10N floats, SoA, one sensitivity per
+ * stored moment (rho, u_x, u_y, u_z, Pi xx, yy, zz, xy, xz, yz); lam_t may
+ * not alias lam_t1.  Uses tau, force and faces of h.
+ * Errors: TSLB_E_UNSUPPORTED unless storage is FP32 and no face is an
+ * inlet/outlet (periodic and wall faces are supported).                     */
+int tslb_adjoint_step(tslb_handle h, const void *state_t, const void *state_t1, const float *lam_t1, float *lam_t,
+                      float *dg_accum, void *stream);
+
+/* Seed of the adjoint: lam = dL/dM for the objective at a raw state
+ * (TSLB_OBJ_KINETIC_ENERGY: L = 1/2 sum_fluid rho |u|^2, so lam_rho =
+ * |u|^2 / 2, lam_u = rho u, lam_Pi = 0; zero on non-fluid nodes).          */
+int tslb_adjoint_seed(tslb_handle h, const void *state, int objective, float *lam, void *stream);
+
+/* Checkpointed rollout for gradients (recompute-every-K scheme).
+ * tslb_rollout_workspace_bytes: device bytes needed for nsteps with a
+ * checkpoint every `every` steps.  tslb_rollout_forward advances the
+ * handle by nsteps, storing a raw snapshot in `ws` at the start of every
+ * segment.  tslb_rollout_backward then takes lam (10N, in: dL/dM at the
+ * final level, out: dL/dM at the initial level) and accumulates dL/dg into
+ * dg_accum (3N, may be NULL), recomputing each segment once from its
+ * checkpoint and running tslb_adjoint_step backwards through it; the
+ * handle's state is left at an unspecified level.                          */
+size_t tslb_rollout_workspace_bytes(tslb_handle h, int nsteps, int every);
+int tslb_rollout_forward(tslb_handle h, int nsteps, int every, void *ws, size_t ws_bytes, void *stream);
+int tslb_rollout_backward(tslb_handle h, int nsteps, int every, void *ws, size_t ws_bytes, float *lam,
+                          float *dg_accum, void *stream);
+
+/* Kernel selection for the update: 0 = the LDS-tiled z-marching kernel
+ * (default), 1 = the direct one-thread-per-node kernel.  Both compute the
+ * same update; the second exists for cross-checks.                          */
+int tslb_set_kernel(tslb_handle h, int variant);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char *tslb_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TSLB_H */

@@ -93,12 +93,14 @@ def _load():
         "or_fpost": (ctypes.c_double, [ctypes.c_int, _D, _D, ctypes.c_double]),
         "or_moments": (None, [_D, _D]),
         "or_node_kind": (ctypes.c_int, [G, ctypes.c_long]),
+        "or_node_kinds": (None, [G, ctypes.c_void_p]),
         "or_ghost_fill": (None, [G, _D, ctypes.c_long]),
         "or_step": (None, [G, _D, _D, _D, ctypes.c_long]),
         "or_round_storage": (None, [G, _D, ctypes.c_int, _D]),
         "or_run": (ctypes.c_int, [G, _D, _D, ctypes.c_long, ctypes.c_int, ctypes.c_int, _D]),
         "or_update_nodes": (None, [G, _D, _D, _L, ctypes.c_long, _D]),
         "or_reduce": (ctypes.c_long, [G, _D, _D]),
+        "or_num_threads": (ctypes.c_int, []),
         "or_splitmix64": (ctypes.c_uint64, [ctypes.c_uint64, ctypes.c_uint64]),
         "or_inlet_xi": (ctypes.c_double, [ctypes.c_uint64, ctypes.c_long, ctypes.c_long, ctypes.c_long,
                                           ctypes.c_int]),
@@ -177,9 +179,10 @@ def moments(f):
 
 
 def node_kinds(grid):
-    lib = _load()
-    return np.array([lib.or_node_kind(ctypes.byref(grid), n) for n in range(grid.n)],
-                    dtype=np.int8).reshape(grid.shape)
+    """Node classes (0 fluid, 1 solid, 2 ghost), shape (nz, ny, nx)."""
+    out = np.empty(grid.shape, dtype=np.int8)
+    _load().or_node_kinds(ctypes.byref(grid), out.ctypes.data)
+    return out
 
 
 def ghost_fill(grid, st, t=0):
@@ -227,6 +230,11 @@ def reduce(grid, st):
     out = np.zeros(5)
     bad = _load().or_reduce(ctypes.byref(grid), _p(st), _p(out))
     return out, bad
+
+
+def num_threads():
+    """OpenMP threads the oracle's parallel loops use."""
+    return _load().or_num_threads()
 
 
 def splitmix64(seed, k):

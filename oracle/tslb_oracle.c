@@ -20,6 +20,7 @@
  */
 #include <complex.h>
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -290,6 +291,13 @@ void or_moments(const double *f, double *m)
 
 int or_node_kind(const or_grid *G, long n) { return node_kind(G, n); }
 
+void or_node_kinds(const or_grid *G, signed char *out)
+{
+    const long N = (long)G->nx * G->ny * G->nz;
+#pragma omp parallel for schedule(static)
+    for (long n = 0; n < N; n++) out[n] = (signed char)node_kind(G, n);
+}
+
 void or_ghost_fill(const or_grid *G, double *st, long t)
 {
     lattice_init();
@@ -367,6 +375,8 @@ long or_reduce(const or_grid *G, const double *st, double *out)
     }
     return bad;
 }
+
+int or_num_threads(void) { return omp_get_max_threads(); }
 
 uint64_t or_splitmix64(uint64_t seed, uint64_t k) { return splitmix64_at(seed, k); }
 double or_inlet_xi(uint64_t seed, long t, long n, long N, int a) { return inlet_xi(seed, t, n, N, a); }

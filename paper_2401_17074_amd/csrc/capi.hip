@@ -1,0 +1,384 @@
+// C-ABI layer of the TSLB library: argument checks, buffer ownership,
+// the time-step loop and the checkpointed gradient driver.  All numerical
+// work happens in the kernels launched from here.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <new>
+
+#include "../../include/tslb.h"
+#include "tslb_internal.h"
+
+using namespace tslb;
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+int fail(int code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+int fail(int code, const char* fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof g_err, fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                          \
+    do {                                                                                       \
+        hipError_t e_ = (expr);                                                                \
+        if (e_ != hipSuccess) return fail(TSLB_E_HIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+inline hipStream_t S(void* s) { return (hipStream_t)s; }
+
+inline bool ghost_kind(int k) { return k == TSLB_INLET || k == TSLB_OUTLET; }
+
+hipError_t run_update(tslb_ctx* h, const void* in, void* out, hipStream_t s) {
+    if (h->kernel == 0) return launch_update_tiled(h->storage, in, out, h->p, s);
+    return launch_update_direct(h->storage, in, out, h->p, s);
+}
+
+// Make `dev` current for the duration of a call.
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) == hipSuccess && prev != dev) (void)hipSetDevice(dev);
+    }
+    ~DeviceGuard() {
+        int cur;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+int ensure_staging(tslb_ctx* h) {
+    if (h->staging) return TSLB_OK;
+    if (hipMalloc((void**)&h->staging, sizeof(float) * 10 * (size_t)h->p.geo.N) != hipSuccess)
+        return fail(TSLB_E_NOMEM, "staging allocation of %zu bytes failed", sizeof(float) * 10 * (size_t)h->p.geo.N);
+    return TSLB_OK;
+}
+
+int fill_ghosts(tslb_ctx* h, void* st, hipStream_t s) {
+    if (!h->has_ghosts) return TSLB_OK;
+    HIP_TRY(launch_ghost_fill(h->storage, st, h->p, h->inlet, h->t, s));
+    return TSLB_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* tslb_last_error(void) { return g_err; }
+
+int tslb_create(int nx, int ny, int nz, int lattice, float tau, const float force[3], const tslb_bc* bc,
+                tslb_handle* out) {
+    if (!out) return fail(TSLB_E_INVALID, "out handle pointer is NULL");
+    *out = nullptr;
+    if (lattice != TSLB_D3Q27) return fail(TSLB_E_UNSUPPORTED, "lattice %d: only D3Q27 (27) is provided", lattice);
+    if (nx < 1 || ny < 1 || nz < 1) return fail(TSLB_E_INVALID, "grid dimensions must be >= 1");
+    if (!(tau > 0.5f) || !isfinite(tau)) return fail(TSLB_E_INVALID, "tau must exceed 1/2 (got %g)", (double)tau);
+    tslb_bc b;
+    memset(&b, 0, sizeof b);
+    if (bc) b = *bc;
+    const int dims[3] = {nx, ny, nz};
+    for (int d = 0; d < 3; ++d) {
+        const int lo = b.face[2 * d], hi = b.face[2 * d + 1];
+        if (lo < 0 || lo > 3 || hi < 0 || hi > 3) return fail(TSLB_E_INVALID, "face kind out of range on axis %d", d);
+        if ((lo == TSLB_PERIODIC) != (hi == TSLB_PERIODIC))
+            return fail(TSLB_E_INVALID, "periodic faces must be paired (axis %d)", d);
+        if (lo != TSLB_PERIODIC && dims[d] < 3)
+            return fail(TSLB_E_INVALID, "a non-periodic axis needs at least 3 nodes (axis %d)", d);
+    }
+    if (b.storage < 0 || b.storage > 2) return fail(TSLB_E_INVALID, "storage kind %d out of range", b.storage);
+    const float def16[3] = {4096.0f, 4096.0f, 65536.0f};
+    for (int k = 0; k < 3; ++k) {
+        float s = b.scale[k];
+        if (b.storage == TSLB_FP32) s = 1.0f;
+        if (s == 0.0f) s = b.storage == TSLB_FP16 ? def16[k] : 1.0f;
+        int e;
+        if (!(s > 0.0f) || frexpf(s, &e) != 0.5f)
+            return fail(TSLB_E_INVALID, "scale[%d] = %g is not a positive power of two", k, (double)s);
+        b.scale[k] = s;
+    }
+    if (!(b.inlet_radius >= 0.0f) || !(b.inlet_noise >= 0.0f))
+        return fail(TSLB_E_INVALID, "inlet radius and noise must be >= 0");
+
+    tslb_ctx* h = new (std::nothrow) tslb_ctx;
+    if (!h) return fail(TSLB_E_NOMEM, "host allocation failed");
+    memset(h, 0, sizeof *h);
+    if (hipGetDevice(&h->device) != hipSuccess) {
+        delete h;
+        return fail(TSLB_E_HIP, "no HIP device");
+    }
+    Geometry& g = h->p.geo;
+    for (int d = 0; d < 3; ++d) {
+        g.n[d] = dims[d];
+        if (b.face[2 * d] == TSLB_PERIODIC) g.periodic |= 1 << d;
+        if (b.face[2 * d] == TSLB_WALL) g.lo_solid |= 1 << d;
+        if (b.face[2 * d + 1] == TSLB_WALL) g.hi_solid |= 1 << d;
+        if (ghost_kind(b.face[2 * d])) g.lo_ghost |= 1 << d;
+        if (ghost_kind(b.face[2 * d + 1])) g.hi_ghost |= 1 << d;
+    }
+    g.N = (long long)nx * ny * nz;
+    h->p.one_minus_omega = (float)(1.0 - 1.0 / (double)tau);
+    for (int a = 0; a < 3; ++a) h->p.force[a] = force ? force[a] : 0.0f;
+    h->p.gfield = nullptr;
+    for (int k = 0; k < 3; ++k) {
+        h->p.scale[k] = b.scale[k];
+        h->p.inv_scale[k] = 1.0f / b.scale[k];
+    }
+    for (int f = 0; f < 6; ++f) h->inlet.face_kind[f] = b.face[f];
+    const double umag = sqrt((double)b.inlet_u[0] * b.inlet_u[0] + (double)b.inlet_u[1] * b.inlet_u[1] +
+                             (double)b.inlet_u[2] * b.inlet_u[2]);
+    for (int a = 0; a < 3; ++a) h->inlet.u[a] = b.inlet_u[a];
+    h->inlet.center[0] = b.inlet_center[0];
+    h->inlet.center[1] = b.inlet_center[1];
+    h->inlet.radius2 = b.inlet_radius * b.inlet_radius;
+    h->inlet.amp = (float)((double)b.inlet_noise * umag);
+    h->inlet.seed = b.seed;
+    h->has_ghosts = (g.lo_ghost | g.hi_ghost) != 0;
+    h->storage = b.storage;
+    h->elem_bytes = b.storage == TSLB_FP32 ? 4 : 2;
+    h->kernel = 0;
+    h->red_blocks = 1024;
+    const size_t bytes = h->elem_bytes * 10 * (size_t)g.N;
+    if (hipMalloc(&h->buf[0], bytes) != hipSuccess || hipMalloc(&h->buf[1], bytes) != hipSuccess ||
+        hipMalloc((void**)&h->red_partials, sizeof(double) * 6 * h->red_blocks) != hipSuccess ||
+        hipMalloc((void**)&h->red_out, sizeof(double) * 6) != hipSuccess) {
+        tslb_destroy(h);
+        return fail(TSLB_E_NOMEM, "device allocation of 2 x %zu bytes failed", bytes);
+    }
+    // rest state: drho = 0, u = 0, Pi = 0 in every format is all-zero bits
+    if (hipMemset(h->buf[0], 0, bytes) != hipSuccess || hipMemset(h->buf[1], 0, bytes) != hipSuccess ||
+        hipDeviceSynchronize() != hipSuccess) {
+        tslb_destroy(h);
+        return fail(TSLB_E_HIP, "initialising the state failed");
+    }
+    *out = h;
+    return TSLB_OK;
+}
+
+int tslb_destroy(tslb_handle h) {
+    if (!h) return TSLB_OK;
+    DeviceGuard dg(h->device);
+    (void)hipDeviceSynchronize();
+    (void)hipFree(h->buf[0]);
+    (void)hipFree(h->buf[1]);
+    (void)hipFree(h->gfield);
+    (void)hipFree(h->staging);
+    (void)hipFree(h->red_partials);
+    (void)hipFree(h->red_out);
+    delete h;
+    return TSLB_OK;
+}
+
+int tslb_set_kernel(tslb_handle h, int variant) {
+    if (!h) return fail(TSLB_E_INVALID, "NULL handle");
+    if (variant < 0 || variant > 1) return fail(TSLB_E_INVALID, "kernel variant %d out of range", variant);
+    h->kernel = variant;
+    return TSLB_OK;
+}
+
+int tslb_set_moments(tslb_handle h, const float* rho, const float* u, const float* pineq, int flags, void* stream) {
+    if (!h || !rho || !u) return fail(TSLB_E_INVALID, "NULL handle or rho/u pointer");
+    DeviceGuard dg(h->device);
+    const size_t N = (size_t)h->p.geo.N;
+    hipStream_t s = S(stream);
+    const float *r = rho, *v = u, *pi = pineq;
+    if (!(flags & TSLB_DEVICE)) {
+        int rc = ensure_staging(h);
+        if (rc) return rc;
+        HIP_TRY(hipMemcpyAsync(h->staging, rho, sizeof(float) * N, hipMemcpyHostToDevice, s));
+        HIP_TRY(hipMemcpyAsync(h->staging + N, u, sizeof(float) * 3 * N, hipMemcpyHostToDevice, s));
+        if (pineq) HIP_TRY(hipMemcpyAsync(h->staging + 4 * N, pineq, sizeof(float) * 6 * N, hipMemcpyHostToDevice, s));
+        r = h->staging;
+        v = h->staging + N;
+        pi = pineq ? h->staging + 4 * N : nullptr;
+    }
+    void* cur = h->buf[h->cur];
+    HIP_TRY(launch_pack(h->storage, r, v, pi, (flags & TSLB_RHO_DEVIATION) ? 1 : 0, cur, h->p, s));
+    int rc = fill_ghosts(h, cur, s);
+    if (rc) return rc;
+    // keep solid nodes identical in both buffers (the update never writes them)
+    HIP_TRY(hipMemcpyAsync(h->buf[1 - h->cur], cur, h->elem_bytes * 10 * N, hipMemcpyDeviceToDevice, s));
+    if (!(flags & TSLB_DEVICE)) HIP_TRY(hipStreamSynchronize(s));
+    return TSLB_OK;
+}
+
+int tslb_get_moments(tslb_handle h, float* rho, float* u, float* pineq, int flags, void* stream) {
+    if (!h) return fail(TSLB_E_INVALID, "NULL handle");
+    DeviceGuard dg(h->device);
+    const size_t N = (size_t)h->p.geo.N;
+    hipStream_t s = S(stream);
+    const int rd = (flags & TSLB_RHO_DEVIATION) ? 1 : 0;
+    if (flags & TSLB_DEVICE) {
+        HIP_TRY(launch_unpack(h->storage, h->buf[h->cur], rho, u, pineq, rd, h->p, s));
+        return TSLB_OK;
+    }
+    int rc = ensure_staging(h);
+    if (rc) return rc;
+    HIP_TRY(launch_unpack(h->storage, h->buf[h->cur], h->staging, h->staging + N, h->staging + 4 * N, rd, h->p, s));
+    if (rho) HIP_TRY(hipMemcpyAsync(rho, h->staging, sizeof(float) * N, hipMemcpyDeviceToHost, s));
+    if (u) HIP_TRY(hipMemcpyAsync(u, h->staging + N, sizeof(float) * 3 * N, hipMemcpyDeviceToHost, s));
+    if (pineq) HIP_TRY(hipMemcpyAsync(pineq, h->staging + 4 * N, sizeof(float) * 6 * N, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return TSLB_OK;
+}
+
+int tslb_set_force_field(tslb_handle h, const float* g, void* stream) {
+    if (!h) return fail(TSLB_E_INVALID, "NULL handle");
+    DeviceGuard dg(h->device);
+    const size_t N = (size_t)h->p.geo.N;
+    if (!g) {
+        h->p.gfield = nullptr;
+        return TSLB_OK;
+    }
+    if (!h->gfield && hipMalloc((void**)&h->gfield, sizeof(float) * 3 * N) != hipSuccess)
+        return fail(TSLB_E_NOMEM, "force-field allocation failed");
+    HIP_TRY(hipMemcpyAsync(h->gfield, g, sizeof(float) * 3 * N, hipMemcpyDeviceToDevice, S(stream)));
+    h->p.gfield = h->gfield;
+    return TSLB_OK;
+}
+
+int tslb_step(tslb_handle h, int nsteps, void* stream) {
+    if (!h) return fail(TSLB_E_INVALID, "NULL handle");
+    if (nsteps < 0) return fail(TSLB_E_INVALID, "nsteps must be >= 0");
+    DeviceGuard dg(h->device);
+    hipStream_t s = S(stream);
+    for (int k = 0; k < nsteps; ++k) {
+        void* in = h->buf[h->cur];
+        void* out = h->buf[1 - h->cur];
+        HIP_TRY(run_update(h, in, out, s));
+        h->cur = 1 - h->cur;
+        h->t += 1;
+        int rc = fill_ghosts(h, out, s);
+        if (rc) return rc;
+    }
+    return TSLB_OK;
+}
+
+int64_t tslb_get_time(tslb_handle h) { return h ? h->t : -1; }
+
+int tslb_set_time(tslb_handle h, int64_t t) {
+    if (!h || t < 0) return fail(TSLB_E_INVALID, "NULL handle or negative level");
+    h->t = t;
+    return TSLB_OK;
+}
+
+int tslb_reduce(tslb_handle h, double out[5], void* stream) {
+    if (!h || !out) return fail(TSLB_E_INVALID, "NULL handle or output");
+    DeviceGuard dg(h->device);
+    hipStream_t s = S(stream);
+    double host[6];
+    HIP_TRY(launch_reduce(h->storage, h->buf[h->cur], h->red_partials, h->red_blocks, h->red_out, h->p, s));
+    HIP_TRY(hipMemcpyAsync(host, h->red_out, sizeof host, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    for (int k = 0; k < 5; ++k) out[k] = host[k];
+    if (host[5] != 0.0) return fail(TSLB_E_UNSTABLE, "%.0f fluid nodes hold NaN or Inf moments", host[5]);
+    return TSLB_OK;
+}
+
+size_t tslb_state_bytes(tslb_handle h) { return h ? h->elem_bytes * 10 * (size_t)h->p.geo.N : 0; }
+
+int tslb_save_state(tslb_handle h, void* dst, void* stream) {
+    if (!h || !dst) return fail(TSLB_E_INVALID, "NULL handle or destination");
+    DeviceGuard dg(h->device);
+    HIP_TRY(hipMemcpyAsync(dst, h->buf[h->cur], tslb_state_bytes(h), hipMemcpyDeviceToDevice, S(stream)));
+    return TSLB_OK;
+}
+
+int tslb_load_state(tslb_handle h, const void* src, void* stream) {
+    if (!h || !src) return fail(TSLB_E_INVALID, "NULL handle or source");
+    DeviceGuard dg(h->device);
+    HIP_TRY(hipMemcpyAsync(h->buf[h->cur], src, tslb_state_bytes(h), hipMemcpyDeviceToDevice, S(stream)));
+    HIP_TRY(hipMemcpyAsync(h->buf[1 - h->cur], src, tslb_state_bytes(h), hipMemcpyDeviceToDevice, S(stream)));
+    return TSLB_OK;
+}
+
+int tslb_adjoint_seed(tslb_handle h, const void* state, int objective, float* lam, void* stream) {
+    if (!h || !state || !lam) return fail(TSLB_E_INVALID, "NULL argument");
+    if (objective != TSLB_OBJ_KINETIC_ENERGY) return fail(TSLB_E_UNSUPPORTED, "objective %d", objective);
+    if (h->storage != TSLB_FP32) return fail(TSLB_E_UNSUPPORTED, "the adjoint needs FP32 storage");
+    DeviceGuard dg(h->device);
+    HIP_TRY(launch_adjoint_seed((const float*)state, lam, h->p, S(stream)));
+    return TSLB_OK;
+}
+
+int tslb_adjoint_step(tslb_handle h, const void* state_t, const void* state_t1, const float* lam_t1, float* lam_t,
+                      float* dg_accum, void* stream) {
+    if (!h || !state_t || !state_t1 || !lam_t1 || !lam_t) return fail(TSLB_E_INVALID, "NULL argument");
+    if (lam_t == lam_t1) return fail(TSLB_E_INVALID, "lam_t may not alias lam_t1");
+    if (h->storage != TSLB_FP32) return fail(TSLB_E_UNSUPPORTED, "the adjoint needs FP32 storage");
+    if (h->has_ghosts) return fail(TSLB_E_UNSUPPORTED, "the adjoint does not differentiate inlet/outlet ghosts");
+    DeviceGuard dg(h->device);
+    HIP_TRY(launch_adjoint_step((const float*)state_t, (const float*)state_t1, lam_t1, lam_t, dg_accum, h->p,
+                                S(stream)));
+    return TSLB_OK;
+}
+
+size_t tslb_rollout_workspace_bytes(tslb_handle h, int nsteps, int every) {
+    if (!h || nsteps < 1 || every < 1) return 0;
+    const size_t nseg = (size_t)((nsteps + every - 1) / every);
+    const size_t sb = tslb_state_bytes(h);
+    return (nseg + (size_t)every + 1) * sb + sizeof(float) * 10 * (size_t)h->p.geo.N;
+}
+
+int tslb_rollout_forward(tslb_handle h, int nsteps, int every, void* ws, size_t ws_bytes, void* stream) {
+    if (!h || !ws || nsteps < 1 || every < 1) return fail(TSLB_E_INVALID, "bad rollout arguments");
+    if (ws_bytes < tslb_rollout_workspace_bytes(h, nsteps, every)) return fail(TSLB_E_INVALID, "workspace too small");
+    const size_t sb = tslb_state_bytes(h);
+    char* ck = (char*)ws;
+    for (int s0 = 0, seg = 0; s0 < nsteps; s0 += every, ++seg) {
+        int rc = tslb_save_state(h, ck + (size_t)seg * sb, stream);
+        if (rc) return rc;
+        rc = tslb_step(h, (nsteps - s0 < every) ? nsteps - s0 : every, stream);
+        if (rc) return rc;
+    }
+    return TSLB_OK;
+}
+
+int tslb_rollout_backward(tslb_handle h, int nsteps, int every, void* ws, size_t ws_bytes, float* lam,
+                          float* dg_accum, void* stream) {
+    if (!h || !ws || !lam || nsteps < 1 || every < 1) return fail(TSLB_E_INVALID, "bad rollout arguments");
+    if (ws_bytes < tslb_rollout_workspace_bytes(h, nsteps, every)) return fail(TSLB_E_INVALID, "workspace too small");
+    DeviceGuard dg(h->device);
+    hipStream_t s = S(stream);
+    const size_t sb = tslb_state_bytes(h);
+    const int nseg = (nsteps + every - 1) / every;
+    char* ck = (char*)ws;
+    char* seg_states = ck + (size_t)nseg * sb;
+    float* lam_tmp = (float*)(seg_states + (size_t)(every + 1) * sb);
+    float* a = lam;      // holds lambda at the current level
+    float* b = lam_tmp;
+    const int64_t t_end = h->t;
+    for (int seg = nseg - 1; seg >= 0; --seg) {
+        const int s0 = seg * every;
+        const int len = (nsteps - s0 < every) ? nsteps - s0 : every;
+        // recompute the segment once from its checkpoint
+        int rc = tslb_load_state(h, ck + (size_t)seg * sb, stream);
+        if (rc) return rc;
+        h->t = t_end - nsteps + s0;
+        rc = tslb_save_state(h, seg_states, stream);
+        if (rc) return rc;
+        for (int k = 1; k <= len; ++k) {
+            rc = tslb_step(h, 1, stream);
+            if (rc) return rc;
+            rc = tslb_save_state(h, seg_states + (size_t)k * sb, stream);
+            if (rc) return rc;
+        }
+        for (int k = len - 1; k >= 0; --k) {
+            rc = tslb_adjoint_step(h, seg_states + (size_t)k * sb, seg_states + (size_t)(k + 1) * sb, a, b,
+                                   dg_accum, stream);
+            if (rc) return rc;
+            float* tmp = a;
+            a = b;
+            b = tmp;
+        }
+    }
+    if (a != lam) HIP_TRY(hipMemcpyAsync(lam, a, sizeof(float) * 10 * (size_t)h->p.geo.N, hipMemcpyDeviceToDevice, s));
+    return TSLB_OK;
+}
+
+}  // extern "C"

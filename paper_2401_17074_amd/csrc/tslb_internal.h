@@ -1,0 +1,67 @@
+// Host-side context of a TSLB solver handle and the launchers each kernel
+// translation unit exports to the C-ABI layer.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "tslb_device.h"
+
+namespace tslb {
+
+// Runtime parameters every update launch needs.
+struct StepParams {
+    Geometry geo;
+    float one_minus_omega;   // 1 - 1/tau
+    float force[3];          // uniform acceleration (used when gfield == nullptr)
+    const float* gfield;     // optional per-node acceleration, 3N SoA
+    float scale[3];          // storage scales (drho, u, Pi); 1 for FP32
+    float inv_scale[3];
+};
+
+// Inflow description for the ghost refill (Section 2.3).
+struct InletParams {
+    int face_kind[6];
+    float u[3];
+    float center[2];
+    float radius2;
+    float amp;               // noise * |u|
+    uint64_t seed;
+};
+
+// Launchers (stream-ordered, no synchronisation).  `storage` selects the
+// stored format (0 FP32, 1 FP16, 2 BF16); buffers are the raw state arrays.
+hipError_t launch_update_direct(int storage, const void* in, void* out, const StepParams& p, hipStream_t s);
+hipError_t launch_update_tiled(int storage, const void* in, void* out, const StepParams& p, hipStream_t s);
+hipError_t launch_ghost_fill(int storage, void* st, const StepParams& p, const InletParams& q, int64_t t,
+                             hipStream_t s);
+hipError_t launch_pack(int storage, const float* rho, const float* u, const float* pi, int rho_dev, void* st,
+                       const StepParams& p, hipStream_t s);
+hipError_t launch_unpack(int storage, const void* st, float* rho, float* u, float* pi, int rho_dev,
+                         const StepParams& p, hipStream_t s);
+// FP64 partial sums: writes 5 sums + 1 non-finite count (as double) into out6 (device).
+hipError_t launch_reduce(int storage, const void* st, double* partials, int nblocks, double* out6,
+                         const StepParams& p, hipStream_t s);
+hipError_t launch_adjoint_seed(const float* st, float* lam, const StepParams& p, hipStream_t s);
+hipError_t launch_adjoint_step(const float* st0, const float* st1, const float* lam1, float* lam0, float* dg,
+                               const StepParams& p, hipStream_t s);
+
+}  // namespace tslb
+
+struct tslb_ctx {
+    int device;
+    tslb::StepParams p;
+    tslb::InletParams inlet;
+    int storage;
+    size_t elem_bytes;       // bytes per stored value
+    void* buf[2];            // ping-pong raw states, 10 N values each
+    int cur;                 // index of the buffer holding the current level
+    float* gfield;           // owned copy of the per-node force field (or null)
+    float* staging;          // device staging for host set/get (10 N floats, lazily)
+    double* red_partials;    // reduction partials
+    double* red_out;         // 6 doubles
+    int red_blocks;
+    int64_t t;               // current level
+    int kernel;              // 0 tiled, 1 direct
+    bool has_ghosts;
+};

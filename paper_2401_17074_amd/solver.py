@@ -1,0 +1,134 @@
+"""Object wrapper over the C ABI and the autograd bridge of the adjoint.
+
+Marshalling only: tensors are allocated with torch on the solver's device and
+passed by pointer; every number is produced by the library's kernels.
+"""
+import torch
+
+from . import _binding as C
+
+
+class Solver:
+    """One TSLB solver handle (tslb_create) on the current CUDA/HIP device.
+
+    State tensors exchanged by ``set_state`` / ``get_state`` are float32 of
+    shape (10, nz, ny, nx): rho - 1, u_x, u_y, u_z, Pi^neq xx, yy, zz, xy, xz, yz.
+    """
+
+    def __init__(self, nx, ny, nz, tau, force=(0.0, 0.0, 0.0), faces=(C.TSLB_PERIODIC,) * 6,
+                 storage=C.TSLB_FP32, scale=(0.0, 0.0, 0.0), inlet_u=(0.0, 0.0, 0.0), inlet_center=(0.0, 0.0),
+                 inlet_radius=0.0, inlet_noise=0.0, seed=0, kernel=None):
+        self.shape = (nz, ny, nx)
+        self.N = nx * ny * nz
+        self.device = torch.device("cuda", torch.cuda.current_device())
+        bc = C.make_bc(faces=faces, inlet_u=inlet_u, inlet_center=inlet_center, inlet_radius=inlet_radius,
+                       inlet_noise=inlet_noise, seed=seed, storage=storage, scale=scale)
+        self.h = C.tslb_create(nx, ny, nz, C.TSLB_D3Q27, tau, force, bc)
+        if kernel is not None:
+            C.tslb_set_kernel(self.h, kernel)
+
+    def close(self):
+        if self.h is not None:
+            C.tslb_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_kernel(self, variant):
+        C.tslb_set_kernel(self.h, variant)
+
+    def set_state(self, st):
+        st = torch.as_tensor(st, dtype=torch.float32).to(self.device).contiguous()
+        assert st.shape == (10,) + self.shape
+        C.tslb_set_moments(self.h, st[0], st[1:4], st[4:10], C.TSLB_DEVICE | C.TSLB_RHO_DEVIATION)
+
+    def get_state(self):
+        st = torch.empty((10,) + self.shape, dtype=torch.float32, device=self.device)
+        C.tslb_get_moments(self.h, st[0], st[1:4], st[4:10], C.TSLB_DEVICE | C.TSLB_RHO_DEVIATION)
+        return st
+
+    def set_force_field(self, g):
+        if g is None:
+            C.tslb_set_force_field(self.h, None)
+            return
+        g = torch.as_tensor(g, dtype=torch.float32).to(self.device).contiguous()
+        assert g.shape == (3,) + self.shape
+        C.tslb_set_force_field(self.h, g)
+
+    def step(self, n=1):
+        C.tslb_step(self.h, n)
+
+    @property
+    def t(self):
+        return C.tslb_get_time(self.h)
+
+    @t.setter
+    def t(self, value):
+        C.tslb_set_time(self.h, value)
+
+    def reduce(self, check=True):
+        """FP64 (mass, momentum x3, kinetic energy) over fluid nodes; synchronises."""
+        out, rc = C.tslb_reduce(self.h, check=check)
+        return out, rc
+
+    def state_bytes(self):
+        return C.tslb_state_bytes(self.h)
+
+    def save_raw(self, dst=None):
+        if dst is None:
+            dst = torch.empty(self.state_bytes(), dtype=torch.uint8, device=self.device)
+        C.tslb_save_state(self.h, dst)
+        return dst
+
+    def load_raw(self, src):
+        C.tslb_load_state(self.h, src)
+
+    def adjoint_step(self, raw_t, raw_t1, lam_t1, dg=None):
+        lam_t = torch.empty_like(lam_t1)
+        C.tslb_adjoint_step(self.h, raw_t, raw_t1, lam_t1, lam_t, dg)
+        return lam_t
+
+    def adjoint_seed(self, raw):
+        lam = torch.empty((10,) + self.shape, dtype=torch.float32, device=self.device)
+        C.tslb_adjoint_seed(self.h, raw, lam)
+        return lam
+
+
+class TslbRollout(torch.autograd.Function):
+    """L = 1/2 sum rho |u|^2 after `nsteps` steps from (rho = 1, u0, Pi = 0)
+    under the force field g, with checkpoints every `every` steps.
+
+    forward(g (3, nz, ny, nx), u0 (3, nz, ny, nx), solver, nsteps, every) -> L
+    (float64 scalar); backward returns dL/dg and dL/du0 from the library's
+    discrete adjoint, recomputing each checkpointed segment once.
+    """
+
+    @staticmethod
+    def forward(ctx, g, u0, solver, nsteps, every):
+        st = torch.zeros((10,) + solver.shape, dtype=torch.float32, device=solver.device)
+        st[1:4] = u0.detach().to(torch.float32)
+        solver.t = 0
+        solver.set_force_field(g.detach())
+        solver.set_state(st)
+        nbytes = C.tslb_rollout_workspace_bytes(solver.h, nsteps, every)
+        ws = torch.empty(nbytes, dtype=torch.uint8, device=solver.device)
+        C.tslb_rollout_forward(solver.h, nsteps, every, ws)
+        final = solver.save_raw()
+        (mass, px, py, pz, ke), _ = solver.reduce()
+        ctx.solver, ctx.nsteps, ctx.every = solver, nsteps, every
+        ctx.save_for_backward(ws, final)
+        return torch.tensor(ke, dtype=torch.float64, device=solver.device)
+
+    @staticmethod
+    def backward(ctx, dL):
+        ws, final = ctx.saved_tensors
+        solver = ctx.solver
+        lam = solver.adjoint_seed(final)
+        dg = torch.zeros((3,) + solver.shape, dtype=torch.float32, device=solver.device)
+        C.tslb_rollout_backward(solver.h, ctx.nsteps, ctx.every, ws, lam, dg)
+        scale = dL.to(torch.float32)
+        return dg * scale, lam[1:4] * scale, None, None, None

@@ -1,0 +1,99 @@
+"""GPU discrete adjoint against the FP64 oracle adjoint (which is itself
+pinned by the dot-product identity and by FP64 central differences in the
+CPU suite).  All calls go through the C ABI."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from helpers import gpu_solver, oracle_grid, to_device_state
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_2401_17074_amd  # noqa: F401
+    torch.cuda.set_device(0)
+
+
+def _rel(a, b):
+    return float(np.abs(a - b).max() / np.abs(b).max())
+
+
+@pytest.mark.parametrize("faces", [(0,) * 6, (0, 0, 1, 1, 0, 0)])
+def test_one_adjoint_step_matches_oracle(faces):
+    import torch
+    case = W.Case("adj1", 19, 14, 11, 0.62, faces=faces)
+    st0 = W.to_fp32(W.random_state(case.shape, seed=201, u_amp=0.05, pi_amp=2e-3))
+    g = W.random_force(case.shape, seed=202, amp=1e-4).astype(np.float32).astype(np.float64)
+    lam1 = np.random.default_rng(203).standard_normal(st0.shape).astype(np.float32).astype(np.float64)
+    G = oracle_grid(case)
+    kinds = oracle.node_kinds(G)
+    lam1[:, kinds != 0] = 0.0
+    s = gpu_solver(case)
+    s.set_force_field(g)
+    s.set_state(to_device_state(st0))
+    raw0 = s.save_raw()
+    s.step(1)
+    raw1 = s.save_raw()
+    lam1_t = torch.tensor(lam1, dtype=torch.float32, device="cuda")
+    dg = torch.zeros((3,) + case.shape, dtype=torch.float32, device="cuda")
+    lam0 = s.adjoint_step(raw0, raw1, lam1_t, dg).double().cpu().numpy()
+    dg = dg.double().cpu().numpy()
+    s.close()
+    want_lam, want_dg = oracle.adjoint_step(G, st0, lam1, g)
+    assert _rel(lam0, want_lam) < 1e-5
+    assert _rel(dg, want_dg) < 1e-5
+
+
+def test_checkpointed_rollout_gradient_matches_oracle():
+    """TslbRollout (checkpoint every 7 of 30 steps) on a 16^3 forced periodic
+    box: dL/dg and dL/du0 against the oracle's stored-trajectory adjoint."""
+    import torch
+    from paper_2401_17074_amd import TslbRollout
+    case = W.adjoint_case(n=16, steps=30, ckpt=7)
+    st0, g = W.adjoint_inputs(case)
+    st0 = W.to_fp32(st0)
+    g = g.astype(np.float32).astype(np.float64)
+    G = oracle_grid(case)
+    L_or, lam0_or, dg_or = oracle.rollout_grad(G, st0, case.steps, g)
+    s = gpu_solver(case)
+    gt = torch.tensor(g, dtype=torch.float32, device="cuda", requires_grad=True)
+    ut = torch.tensor(st0[1:4], dtype=torch.float32, device="cuda", requires_grad=True)
+    L = TslbRollout.apply(gt, ut, s, case.steps, case.extra["ckpt"])
+    L.backward()
+    s.close()
+    assert float(L) == pytest.approx(L_or, rel=1e-5)
+    assert _rel(gt.grad.double().cpu().numpy(), dg_or) < 1e-4
+    assert _rel(ut.grad.double().cpu().numpy(), lam0_or[1:4]) < 1e-4
+
+
+def test_full_size_adjoint_step_sampled():
+    """64^3 forced periodic box of the differentiable workload: one adjoint
+    step at the step the rollout uses, checked at sampled nodes."""
+    import torch
+    case = W.adjoint_case()
+    st0, g = W.adjoint_inputs(case)
+    st0 = W.to_fp32(st0)
+    g = g.astype(np.float32).astype(np.float64)
+    G = oracle_grid(case)
+    s = gpu_solver(case)
+    s.set_force_field(g)
+    s.set_state(to_device_state(st0))
+    s.step(3)
+    raw0 = s.save_raw()
+    pre = s.get_state().double().cpu().numpy()
+    pre[0] += 1.0
+    s.step(1)
+    raw1 = s.save_raw()
+    lam1 = s.adjoint_seed(raw1)
+    lam0 = s.adjoint_step(raw0, raw1, lam1).double().cpu().numpy()
+    lam1 = lam1.double().cpu().numpy()
+    s.close()
+    idx = W.sample_nodes(case, 600, 204)
+    want, _ = oracle.adjoint_nodes(G, pre, lam1, idx, g)
+    got = lam0.reshape(10, -1)[:, idx]
+    assert _rel(got, want) < 1e-5

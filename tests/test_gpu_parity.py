@@ -1,0 +1,190 @@
+"""GPU parity of the forward update against the FP64 oracle (all through the
+C ABI).  Tolerances: the spec bar is max relative error <= 1e-5 in
+rho and u after 100 laminar steps (Taylor-Green 32^3); single steps from the
+same binary32 state are held to a few binary32 ulps of the largest value
+(normwise 2e-6 for u, 1e-7 absolute for rho - 1; Pi^neq is the difference
+of sum f c c and rho u u, so its bar is 32 binary32 ulps of the larger of
+max |u|^2 and max |Pi|, the scale of the terms that cancel).  Full-size
+workloads are checked at a seeded sample of nodes that the oracle updates
+one by one from the GPU's own pre-step state, plus properties (conservation
+in FP64 reductions) that hold at any size."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from helpers import abs_err, from_device_state, gpu_solver, oracle_grid, rel_err, to_device_state
+
+pytestmark = pytest.mark.gpu
+
+KERNELS = [0, 1]
+EPS32 = float(np.finfo(np.float32).eps)
+
+
+def pi_tol(want):
+    return 32 * EPS32 * max(float(np.abs(want[1:4]).max()) ** 2, float(np.abs(want[4:]).max()))
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_2401_17074_amd  # noqa: F401  (fails loudly if the HIP library is missing)
+    torch.cuda.set_device(0)
+
+
+@pytest.mark.parametrize("kernel", KERNELS)
+def test_taylor_green_100_steps(kernel):
+    case = W.tgv_case()
+    st0 = W.to_fp32(W.tgv_state(case.nx, case.extra["u0"]))
+    G = oracle_grid(case)
+    want = oracle.run(G, st0, case.steps)
+    s = gpu_solver(case, kernel=kernel)
+    s.set_state(to_device_state(st0))
+    s.step(case.steps)
+    got = from_device_state(s.get_state())
+    red, rc = s.reduce()
+    s.close()
+    e_u = rel_err(got[1:4], want[1:4])
+    e_rho = rel_err(got[0], want[0])
+    print("TGV kernel=%d rel err u %.3e rho %.3e" % (kernel, e_u, e_rho))
+    assert e_u <= 1e-5 and e_rho <= 1e-5
+    # decay of the Taylor-Green mode at nu = (tau - 1/2)/3
+    mode = st0[1]
+    amp = (got[1] * mode).sum() / (mode * mode).sum()
+    amp_or = (want[1] * mode).sum() / (mode * mode).sum()
+    assert amp == pytest.approx(amp_or, rel=1e-5)
+    # FP64 reductions of the GPU state: mass and momentum conserved up to the
+    # binary32 rounding of the stored u (one ulp of max |u| per node at most)
+    r0, _ = oracle.reduce(G, st0)
+    assert abs(red[0] - r0[0]) < 1e-9 * r0[0]
+    assert np.abs(np.array(red[1:4]) - r0[1:4]).max() < case.nodes * EPS32 * np.abs(st0[1:4]).max()
+
+
+CASES = [
+    ("periodic", (0, 0, 0, 0, 0, 0)),
+    ("walls_y", (0, 0, 1, 1, 0, 0)),
+    ("walls_xz", (1, 1, 0, 0, 1, 1)),
+    ("ghosts", (3, 3, 3, 3, 3, 3)),
+]
+
+
+@pytest.mark.parametrize("kernel", KERNELS)
+@pytest.mark.parametrize("name,faces", CASES)
+def test_random_state_ragged_grid(kernel, name, faces):
+    """Odd sizes that span several tiles with ragged tails, random moments,
+    per-node force field; 1 and then 6 more steps against the oracle."""
+    case = W.Case(name, 71, 37, 23, 0.57, faces=faces)
+    st0 = W.to_fp32(W.random_state(case.shape, seed=101))
+    g = W.random_force(case.shape, seed=102, amp=1e-5).astype(np.float32).astype(np.float64)
+    G = oracle_grid(case)
+    st0 = oracle.ghost_fill(G, st0, 0)
+    kinds = oracle.node_kinds(G)
+    s = gpu_solver(case, kernel=kernel)
+    s.set_force_field(g)
+    s.set_state(to_device_state(st0))
+    s.step(1)
+    got1 = from_device_state(s.get_state())
+    want1 = oracle.step(G, st0, g)
+    fl = kinds == 0
+    assert abs_err(got1[0], want1[0], fl) < 1e-7
+    assert rel_err(got1[1:4], want1[1:4], fl) < 2e-6
+    assert abs_err(got1[4:], want1[4:], fl) < pi_tol(want1[:, fl])
+    # ghosts are refilled from the GPU's own level-1 interior values
+    if (kinds == 2).any():
+        want_g = oracle.ghost_fill(G, got1, 1)
+        assert abs_err(got1, want_g, kinds == 2) < 1e-7
+    s.step(6)
+    got = from_device_state(s.get_state())
+    s.close()
+    want = oracle.run(G, st0, 7, g)
+    assert rel_err(got[1:4], want[1:4], fl) < 1e-5
+    assert abs_err(got[0], want[0], fl) < 1e-6
+
+
+@pytest.mark.parametrize("kernel", KERNELS)
+def test_small_jet_with_inlet_noise(kernel):
+    case = W.jet_case(nx=48, ny=30, nz=26, D=8.0, steps=30)
+    st0 = W.jet_state(case)
+    G = oracle_grid(case)
+    st0 = oracle.ghost_fill(G, st0, 0)
+    kinds = oracle.node_kinds(G)
+    s = gpu_solver(case, kernel=kernel)
+    s.set_state(to_device_state(st0))
+    got0 = from_device_state(s.get_state())
+    # inlet ghosts at level 0 carry the imposed velocity and the seeded noise
+    assert abs_err(got0[1:4], st0[1:4], kinds == 2) < 1e-8
+    s.step(case.steps)
+    got = from_device_state(s.get_state())
+    s.close()
+    want = oracle.run(G, st0, case.steps)
+    assert rel_err(got[1:4], want[1:4]) < 1e-5
+    assert abs_err(got[0], want[0]) < 1e-6
+
+
+def _sampled_one_step(case, st_pre, got_post, nsamp, seed):
+    G = oracle_grid(case)
+    kinds = oracle.node_kinds(G)
+    idx = W.sample_nodes(case, nsamp, seed, fluid_mask=(kinds == 0))
+    want = oracle.update_nodes(G, st_pre, idx)
+    got = got_post.reshape(10, -1)[:, idx]
+    return got, want, G, kinds
+
+
+@pytest.mark.parametrize("kernel", KERNELS)
+def test_channel_full_size_sampled(kernel):
+    """384x192x192 channel (walls at y = 0, ny - 1), the benchmark launch:
+    20 steps, then one more step checked at 4000 sampled fluid nodes."""
+    case = W.channel_case()
+    st0 = W.to_fp32(W.channel_state(case))
+    s = gpu_solver(case, kernel=kernel)
+    s.set_state(to_device_state(st0))
+    r0, _ = s.reduce()
+    s.step(20)
+    pre = from_device_state(s.get_state())
+    s.step(1)
+    post = from_device_state(s.get_state())
+    r1, rc = s.reduce()
+    s.close()
+    got, want, G, kinds = _sampled_one_step(case, pre, post, 4000, 5)
+    assert np.abs(got[0] - want[0]).max() < 1e-7
+    assert np.abs(got[1:4] - want[1:4]).max() < 2e-6 * np.abs(want[1:4]).max()
+    assert np.abs(got[4:] - want[4:]).max() < pi_tol(want)
+    # mass with bounce-back walls is conserved; momentum gains sum rho g per step
+    assert abs(r1[0] - r0[0]) < 1e-6 * r0[0]
+
+
+@pytest.mark.parametrize("kernel", KERNELS)
+def test_jet_full_size_sampled(kernel):
+    """512x256x256 jet (inlet disc, outflow ghosts elsewhere): 10 steps, then
+    one step checked at sampled fluid nodes, and the ghost refill checked on
+    every ghost node against the rule applied to the GPU's interior."""
+    case = W.jet_case()
+    s = gpu_solver(case, kernel=kernel)
+    s.set_state(to_device_state(W.jet_state(case)))
+    s.step(10)
+    pre = from_device_state(s.get_state())
+    s.step(1)
+    post = from_device_state(s.get_state())
+    s.close()
+    got, want, G, kinds = _sampled_one_step(case, pre, post, 3000, 6)
+    assert np.abs(got[0] - want[0]).max() < 1e-7
+    assert np.abs(got[1:4] - want[1:4]).max() < 2e-6 * max(np.abs(want[1:4]).max(), 1e-3)
+    t = 11
+    regen = oracle.ghost_fill(G, post, t)
+    gh = kinds == 2
+    assert np.abs(regen[:, gh] - post[:, gh]).max() < 1e-8
+
+
+@pytest.mark.parametrize("kernel", KERNELS)
+def test_determinism(kernel):
+    case = W.Case("det", 64, 40, 33, 0.6, faces=(0, 0, 1, 1, 0, 0), force=(1e-6, 0, 0))
+    st0 = W.to_fp32(W.random_state(case.shape, seed=103))
+    outs = []
+    for _ in range(2):
+        s = gpu_solver(case, kernel=kernel)
+        s.set_state(to_device_state(st0))
+        s.step(5)
+        outs.append(s.get_state().cpu().numpy())
+        s.close()
+    assert np.array_equal(outs[0], outs[1])
