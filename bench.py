@@ -194,15 +194,38 @@ def load_traffic(kernel_name, case_name, storage):
     return rec.get("hbm_bytes_per_launch")
 
 
+WORKLOADS = {
+    "channel": lambda W: (lambda c: (c, W.channel_state(c)))(W.channel_case()),
+    "channel512": lambda W: (lambda c: (c, W.channel_state(c)))(W.channel_case(nx=512, ny=256, nz=256)),
+    "jet": lambda W: (lambda c: (c, W.jet_state(c)))(W.jet_case()),
+    "cube512": lambda W: (lambda c: (c, W.tgv_state(c.nx, 0.01)))(W.tgv_case(n=512)),
+    "tgv32": lambda W: (lambda c: (c, W.tgv_state(c.nx, 0.01)))(W.tgv_case()),
+}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--kernel", type=int, default=0, help="0 tiled (default), 1 direct")
+    ap.add_argument("--workload", default="channel", choices=sorted(WORKLOADS),
+                    help="timed workload (default: the 384x192x192 channel)")
     ap.add_argument("--quick", action="store_true", help="only the timed workload (for profiling)")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB 20 times (HBM counter calibration)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+        n = args.copy_calibration * (1 << 20) // 4
+        a = torch.ones(n, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(20):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_per_launch": 2 * n * 4, "launches": 20}))
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU: this build runs on a single MI355X and has no multi-GPU path "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
@@ -213,8 +236,7 @@ def main():
     import workloads as W
     torch.cuda.set_device(0)
 
-    case = W.channel_case(steps=args.steps)
-    st64 = W.channel_state(case)
+    case, st64 = WORKLOADS[args.workload](W)
     s = _solver(case, 0, args.kernel)
     s.set_state(_device_state(st64))
     ms, wall = time_steps(s, args.steps, args.warmup)
@@ -239,8 +261,7 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": case.name, "nodes": case.nodes, "lattice": "D3Q27", "tau": case.tau,
-                   "storage": "fp32", "boundaries": "x,z periodic; bounce-back walls y=0,ny-1",
-                   "kernel": kname, "stable": rc == 0},
+                   "storage": "fp32", "faces": list(case.faces), "kernel": kname, "stable": rc == 0},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": load_traffic(kname, case.name, 0),

@@ -104,12 +104,13 @@ int tslb_destroy(tslb_handle h);
  * memory (else host; the call then synchronises the stream),
  * TSLB_RHO_DEVIATION if `rho` holds rho - 1.  Values are rounded to the
  * storage format; ghost layers are then refilled from the interior (so input
- * ghost values are ignored) and solid nodes are stored as given.           */
+ * ghost values are ignored) and solid (wall) nodes are stored as the rest
+ * state rho = 1, u = 0, Pi = 0 whatever the input holds.                   */
 int tslb_set_moments(tslb_handle h, const float *rho, const float *u, const float *pineq, int flags,
                      void *stream);
 
 /* Read the current state (all nodes; ghosts hold their fill values, solid
- * nodes what was last set).  Any output pointer may be NULL.  Same flags as
+ * nodes the rest state).  Any output pointer may be NULL.  Same flags as
  * tslb_set_moments; host reads synchronise the stream.                      */
 int tslb_get_moments(tslb_handle h, float *rho, float *u, float *pineq, int flags, void *stream);
 

@@ -11,7 +11,9 @@ FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++20", "-fPIC", "-Wall",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 
 
-def build(verbose=False):
+def build(verbose=False, defines=()):
+    """Compile and link libtslb.so.  `defines` (e.g. ("TSLB_TILE_Z=64",)) are
+    build-time tuning overrides of the tiled kernel's tile shape."""
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
     obj_dir = os.path.join(ROOT, "_build")
     os.makedirs(obj_dir, exist_ok=True)
@@ -20,7 +22,7 @@ def build(verbose=False):
     for src in SOURCES:
         obj = os.path.join(obj_dir, src.replace(".hip", ".o"))
         objs.append(obj)
-        cmd = [hipcc] + FLAGS + ["-c", os.path.join(HERE, "csrc", src), "-o", obj]
+        cmd = [hipcc] + FLAGS + ["-D" + d for d in defines] + ["-c", os.path.join(HERE, "csrc", src), "-o", obj]
         procs.append((cmd, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)))
     failed = []
     for cmd, p in procs:
@@ -42,4 +44,4 @@ def build(verbose=False):
 
 
 if __name__ == "__main__":
-    build(verbose=True)
+    build(verbose=True, defines=tuple(sys.argv[1:]))

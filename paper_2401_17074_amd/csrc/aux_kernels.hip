@@ -77,15 +77,22 @@ __global__ void ghost_fill_kernel(typename S::T* __restrict__ st, StepParams p, 
 template <class S>
 __global__ void pack_kernel(const float* __restrict__ rho, const float* __restrict__ u, const float* __restrict__ pi,
                             int rho_dev, typename S::T* __restrict__ st, StepParams p) {
-    const long long N = p.geo.N;
+    const Geometry& g = p.geo;
+    const long long N = g.N;
     const long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (n >= N) return;
+    // wall nodes hold the zero deviation (rest state): the tiled update
+    // relies on them emitting nothing
+    const int x = (int)(n % g.n[0]);
+    const int y = (int)((n / g.n[0]) % g.n[1]);
+    const int z = (int)(n / ((long long)g.n[0] * g.n[1]));
+    const float keep = is_solid(g, x, y, z) ? 0.0f : 1.0f;
     const float r = rho[n];
-    st[n] = S::store(rho_dev ? r : r - 1.0f, p.scale[0]);
+    st[n] = S::store(keep * (rho_dev ? r : r - 1.0f), p.scale[0]);
 #pragma unroll
-    for (int a = 0; a < 3; ++a) st[(1 + a) * N + n] = S::store(u[a * N + n], p.scale[1]);
+    for (int a = 0; a < 3; ++a) st[(1 + a) * N + n] = S::store(keep * u[a * N + n], p.scale[1]);
 #pragma unroll
-    for (int k = 0; k < 6; ++k) st[(4 + k) * N + n] = S::store(pi ? pi[k * N + n] : 0.0f, p.scale[2]);
+    for (int k = 0; k < 6; ++k) st[(4 + k) * N + n] = S::store(pi ? keep * pi[k * N + n] : 0.0f, p.scale[2]);
 }
 
 template <class S>

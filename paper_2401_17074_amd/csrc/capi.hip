@@ -37,7 +37,11 @@ inline hipStream_t S(void* s) { return (hipStream_t)s; }
 inline bool ghost_kind(int k) { return k == TSLB_INLET || k == TSLB_OUTLET; }
 
 hipError_t run_update(tslb_ctx* h, const void* in, void* out, hipStream_t s) {
-    if (h->kernel == 0) return launch_update_tiled(h->storage, in, out, h->p, s);
+    if (h->kernel == 0) {
+        hipError_t e = launch_update_tiled(h->storage, in, out, h->p, s);
+        if (e != hipSuccess) return e;
+        return launch_wall_fixup(h->storage, in, out, h->p, s);
+    }
     return launch_update_direct(h->storage, in, out, h->p, s);
 }
 
@@ -139,6 +143,15 @@ int tslb_create(int nx, int ny, int nz, int lattice, float tau, const float forc
     h->inlet.amp = (float)((double)b.inlet_noise * umag);
     h->inlet.seed = b.seed;
     h->has_ghosts = (g.lo_ghost | g.hi_ghost) != 0;
+    // layers next to wall faces (raw sums of the tiled update, fix-up pass)
+    h->p.wall_nodes = 0;
+    for (int f = 0; f < 6; ++f) {
+        const int d = f >> 1, d1 = d == 0 ? 1 : 0, d2 = d == 2 ? 1 : 2;
+        const bool wall = (f & 1) ? ((g.hi_solid >> d) & 1) : ((g.lo_solid >> d) & 1);
+        h->p.wall_off[f] = wall ? h->p.wall_nodes : -1;
+        if (wall) h->p.wall_nodes += (long long)dims[d1] * dims[d2];
+    }
+    h->p.wall_side = nullptr;
     h->storage = b.storage;
     h->elem_bytes = b.storage == TSLB_FP32 ? 4 : 2;
     h->kernel = 0;
@@ -146,7 +159,9 @@ int tslb_create(int nx, int ny, int nz, int lattice, float tau, const float forc
     const size_t bytes = h->elem_bytes * 10 * (size_t)g.N;
     if (hipMalloc(&h->buf[0], bytes) != hipSuccess || hipMalloc(&h->buf[1], bytes) != hipSuccess ||
         hipMalloc((void**)&h->red_partials, sizeof(double) * 6 * h->red_blocks) != hipSuccess ||
-        hipMalloc((void**)&h->red_out, sizeof(double) * 6) != hipSuccess) {
+        hipMalloc((void**)&h->red_out, sizeof(double) * 6) != hipSuccess ||
+        (h->p.wall_nodes > 0 &&
+         hipMalloc((void**)&h->p.wall_side, sizeof(float) * 10 * (size_t)h->p.wall_nodes) != hipSuccess)) {
         tslb_destroy(h);
         return fail(TSLB_E_NOMEM, "device allocation of 2 x %zu bytes failed", bytes);
     }
@@ -170,6 +185,7 @@ int tslb_destroy(tslb_handle h) {
     (void)hipFree(h->staging);
     (void)hipFree(h->red_partials);
     (void)hipFree(h->red_out);
+    (void)hipFree(h->p.wall_side);
     delete h;
     return TSLB_OK;
 }

@@ -62,6 +62,27 @@ __device__ __forceinline__ bool is_fluid(const Geometry& g, int x, int y, int z)
     return f;
 }
 
+// Wall face next to a fluid node (the first of -x, +x, -y, +y, -z, +z whose
+// wall layer is a neighbour), or -1.  Faces: bit d of lo_solid / hi_solid.
+__device__ __forceinline__ int first_wall_face(const Geometry& g, const int c[3]) {
+#pragma unroll
+    for (int f = 0; f < 6; ++f) {
+        const int d = f >> 1;
+        const bool wall = (f & 1) ? ((g.hi_solid >> d) & 1) : ((g.lo_solid >> d) & 1);
+        const int layer = (f & 1) ? g.n[d] - 2 : 1;
+        if (wall && c[d] == layer) return f;
+    }
+    return -1;
+}
+
+// Position of a node inside the layer of face f: the two transverse
+// coordinates (in x, y, z order) as a + n_a * b.
+__device__ __forceinline__ long long wall_layer_index(const Geometry& g, int f, const int c[3]) {
+    const int d = f >> 1;
+    const int d1 = d == 0 ? 1 : 0, d2 = d == 2 ? 1 : 2;
+    return (long long)c[d1] + (long long)g.n[d1] * c[d2];
+}
+
 // ------------------------------------------------------------------ storage
 // Stored field q of a node: FP32 as is; FP16 / BF16 hold value * scale[q]
 // rounded to nearest even.  Field 0 holds rho - 1.
@@ -184,7 +205,10 @@ struct MomentSums {
 //   drho' = D/216,  u' = J / (216 + D),
 //   Pi'   = (S - J u' - D/3 delta) / 216.
 __device__ __forceinline__ void finalize(const MomentSums& a, float out[10]) {
-    const float inv = 1.0f / (216.0f + a.d);
+    // 1 / (216 + D): hardware reciprocal refined by one Newton step
+    const float den = 216.0f + a.d;
+    float inv = __builtin_amdgcn_rcpf(den);
+    inv = inv * fmaf(-den, inv, 2.0f);
     const float ux = a.j[0] * inv, uy = a.j[1] * inv, uz = a.j[2] * inv;
     const float d3 = a.d * (1.0f / 3.0f);
     out[0] = a.d * kInv216;

@@ -17,6 +17,13 @@ struct StepParams {
     const float* gfield;     // optional per-node acceleration, 3N SoA
     float scale[3];          // storage scales (drho, u, Pi); 1 for FP32
     float inv_scale[3];
+    // Wall-adjacent fluid nodes: the tiled update leaves their raw moment
+    // sums here (FP32, ten per node) and a fix-up pass adds the bounced-back
+    // populations.  The layer next to wall face f starts at wall_off[f]
+    // nodes (-1: face f is not a wall).
+    float* wall_side;
+    long long wall_off[6];
+    long long wall_nodes;
 };
 
 // Inflow description for the ghost refill (Section 2.3).
@@ -33,6 +40,8 @@ struct InletParams {
 // stored format (0 FP32, 1 FP16, 2 BF16); buffers are the raw state arrays.
 hipError_t launch_update_direct(int storage, const void* in, void* out, const StepParams& p, hipStream_t s);
 hipError_t launch_update_tiled(int storage, const void* in, void* out, const StepParams& p, hipStream_t s);
+// Completes the wall-adjacent nodes after launch_update_tiled (walls only).
+hipError_t launch_wall_fixup(int storage, const void* in, void* out, const StepParams& p, hipStream_t s);
 hipError_t launch_ghost_fill(int storage, void* st, const StepParams& p, const InletParams& q, int64_t t,
                              hipStream_t s);
 hipError_t launch_pack(int storage, const float* rho, const float* u, const float* pi, int rho_dev, void* st,

@@ -162,3 +162,29 @@ def test_rollout_gradient_matches_central_differences(oracle):
         h = 1e-4 * np.abs(st0[1:4]).max()
         fd = (loss(st0 + h * du, g) - loss(st0 - h * du, g)) / (2 * h)
         assert (lam0 * du).sum() == pytest.approx(fd, rel=1e-6)
+
+
+def test_uniform_flow_through_inlet_and_outlets_is_a_fixed_point(oracle):
+    """Uniform flow U (any direction) with an inlet disc covering the whole
+    inflow face that imposes U (no noise) and zero-gradient ghosts elsewhere:
+    every ghost equals the interior, so the state must be reproduced exactly.
+    A wrong sign, component or time level in the inlet fill breaks this."""
+    U = np.array([0.04, -0.01, 0.015])
+    for face in range(6):
+        faces = [3] * 6
+        faces[face] = 2
+        G = oracle.make_grid(7, 6, 5, 0.6, faces=faces, inlet_u=U, inlet_center=(2.5, 2.5), inlet_radius=50.0,
+                             inlet_noise=0.0, seed=3)
+        st = W.rest_state(G.shape)
+        st[0] = 1.01
+        st[1:4] = U[:, None, None, None]
+        st = oracle.ghost_fill(G, st, 0)
+        out = oracle.run(G, st, 3)
+        assert np.abs(out - st).max() < 1e-15, face
+    # and a non-matching imposed velocity is not a fixed point
+    G = oracle.make_grid(7, 6, 5, 0.6, faces=(2, 3, 3, 3, 3, 3), inlet_u=-U, inlet_center=(2.5, 2.5),
+                         inlet_radius=50.0)
+    st = W.rest_state(G.shape)
+    st[1:4] = U[:, None, None, None]
+    st = oracle.ghost_fill(G, st, 0)
+    assert np.abs(oracle.run(G, st, 1) - st).max() > 1e-4
