@@ -44,6 +44,7 @@ class Grid(ctypes.Structure):
         ("inlet_radius", ctypes.c_double),
         ("inlet_noise", ctypes.c_double),
         ("seed", ctypes.c_uint64),
+        ("order", ctypes.c_int),
     ]
 
     @property
@@ -56,7 +57,9 @@ class Grid(ctypes.Structure):
 
 
 def make_grid(nx, ny, nz, tau, faces=(PERIODIC,) * 6, force=(0.0, 0.0, 0.0), inlet_u=(0.0, 0.0, 0.0),
-              inlet_center=(0.0, 0.0), inlet_radius=0.0, inlet_noise=0.0, seed=0):
+              inlet_center=(0.0, 0.0), inlet_radius=0.0, inlet_noise=0.0, seed=0, order=3):
+    """order: 3 = the recursive third-order update (Section 2.2), 2 = the
+    regularised second-order update (Eq. (fullstrcoll))."""
     g = Grid()
     g.nx, g.ny, g.nz = nx, ny, nz
     for k in range(6):
@@ -69,6 +72,7 @@ def make_grid(nx, ny, nz, tau, faces=(PERIODIC,) * 6, force=(0.0, 0.0, 0.0), inl
     g.inlet_radius = inlet_radius
     g.inlet_noise = inlet_noise
     g.seed = seed
+    g.order = order
     return g
 
 
@@ -88,9 +92,9 @@ def _load():
     sig = {
         "or_lattice": (None, [ctypes.POINTER(ctypes.c_int), _D, ctypes.POINTER(ctypes.c_int)]),
         "or_hermite": (ctypes.c_double, [ctypes.c_int] * 5),
-        "or_feq": (ctypes.c_double, [ctypes.c_int, ctypes.c_double, _D]),
-        "or_fneq": (ctypes.c_double, [ctypes.c_int, _D, _D]),
-        "or_fpost": (ctypes.c_double, [ctypes.c_int, _D, _D, ctypes.c_double]),
+        "or_feq": (ctypes.c_double, [ctypes.c_int, ctypes.c_double, _D, ctypes.c_int]),
+        "or_fneq": (ctypes.c_double, [ctypes.c_int, _D, _D, ctypes.c_int]),
+        "or_fpost": (ctypes.c_double, [ctypes.c_int, _D, _D, ctypes.c_double, ctypes.c_int]),
         "or_moments": (None, [_D, _D]),
         "or_node_kind": (ctypes.c_int, [G, ctypes.c_long]),
         "or_node_kinds": (None, [G, ctypes.c_void_p]),
@@ -154,21 +158,21 @@ def hermite(i, order, a=0, b=0, g=0):
     return _load().or_hermite(i, order, a, b, g)
 
 
-def feq(i, rho, u):
+def feq(i, rho, u, order=3):
     u = np.ascontiguousarray(u, dtype=np.float64)
-    return _load().or_feq(i, rho, _p(u))
+    return _load().or_feq(i, rho, _p(u), order)
 
 
-def fneq(i, pi6, u):
+def fneq(i, pi6, u, order=3):
     pi6 = np.ascontiguousarray(pi6, dtype=np.float64)
     u = np.ascontiguousarray(u, dtype=np.float64)
-    return _load().or_fneq(i, _p(pi6), _p(u))
+    return _load().or_fneq(i, _p(pi6), _p(u), order)
 
 
-def fpost(i, m, g, omega):
+def fpost(i, m, g, omega, order=3):
     m = np.ascontiguousarray(m, dtype=np.float64)
     g = np.ascontiguousarray(g, dtype=np.float64)
-    return _load().or_fpost(i, _p(m), _p(g), omega)
+    return _load().or_fpost(i, _p(m), _p(g), omega, order)
 
 
 def moments(f):

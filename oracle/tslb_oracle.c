@@ -89,6 +89,7 @@ typedef struct {
     double inlet_radius;
     double inlet_noise; /* relative amplitude of the inlet perturbation */
     uint64_t seed;
+    int order; /* Hermite order of the reconstruction: 3 (Section 2.2) or 2 (Eq. (fullstrcoll)) */
 } or_grid;
 
 static int dim(const or_grid *G, int d) { return d == 0 ? G->nx : (d == 1 ? G->ny : G->nz); }
@@ -262,25 +263,25 @@ double or_hermite(int i, int order, int a, int b, int g)
     return NAN;
 }
 
-double or_feq(int i, double rho, const double *u)
+double or_feq(int i, double rho, const double *u, int order)
 {
     lattice_init();
-    return feq_r(i, rho, u);
+    return feq_r(i, rho, u, order);
 }
 
-double or_fneq(int i, const double *pi6, const double *u)
+double or_fneq(int i, const double *pi6, const double *u, int order)
 {
     lattice_init();
     double pi[3][3];
     for (int a = 0; a < 3; a++)
         for (int b = 0; b < 3; b++) pi[a][b] = pi6[PI_IDX[a][b]];
-    return fneq_r(i, pi, u);
+    return fneq_r(i, pi, u, order);
 }
 
-double or_fpost(int i, const double *m, const double *g, double omega)
+double or_fpost(int i, const double *m, const double *g, double omega, int order)
 {
     lattice_init();
-    return fpost_r(i, m, g, omega);
+    return fpost_r(i, m, g, omega, order);
 }
 
 void or_moments(const double *f, double *m)
@@ -444,7 +445,7 @@ static void adjoint_emit(const or_grid *G, const double *st, const double *gf, l
             m[p] += I * CSTEP;
         else
             g[p - 10] += I * CSTEP;
-        double d = cimag(fpost_c(k, m, g, omega)) / CSTEP;
+        double d = cimag(fpost_c(k, m, g, omega, G->order)) / CSTEP;
         if (p < 10)
             lm[p] += d * lf;
         else

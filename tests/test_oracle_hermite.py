@@ -102,13 +102,16 @@ def test_hermite_tensors_match_definition_and_are_orthogonal(oracle):
     assert np.einsum("i,i,i->", w, H[3][:, 0, 1, 2], H[3][:, 0, 1, 2]) == pytest.approx(CS2 ** 3)
 
 
+@pytest.mark.parametrize("order", [3, 2])
 @pytest.mark.parametrize("seed", [0, 1, 2])
-def test_equilibrium_hermite_coefficients(oracle, seed):
+def test_equilibrium_hermite_coefficients(oracle, seed, order):
+    """Order 3: Eq. (eqts); order 2: Eq. (lbequil), whose third-order
+    Hermite coefficients vanish."""
     rng = np.random.default_rng(seed)
     rho = 1.0 + 0.1 * rng.standard_normal()
     u = 0.1 * rng.standard_normal(3)
     c, w, _ = oracle.lattice()
-    f = np.array([oracle.feq(i, rho, u) for i in range(27)])
+    f = np.array([oracle.feq(i, rho, u, order) for i in range(27)])
     H2 = _H(oracle, 2)
     H3 = _H(oracle, 3)
     assert f.sum() == pytest.approx(rho, rel=1e-14)
@@ -120,20 +123,21 @@ def test_equilibrium_hermite_coefficients(oracle, seed):
     assert np.allclose(np.einsum("i,iab->ab", f, H2), rho * np.outer(u, u), rtol=1e-12, atol=1e-16)
     a3 = np.einsum("i,iabg->abg", f, H3)
     for (a, b, g) in itertools.product(range(3), repeat=3):
-        if len({a, b, g}) == 1:
-            assert a3[a, b, g] == pytest.approx(0.0, abs=1e-16)  # Q_xxx not supported
+        if len({a, b, g}) == 1 or order == 2:
+            assert a3[a, b, g] == pytest.approx(0.0, abs=1e-15)  # Q_xxx not supported / not kept
         else:
             assert a3[a, b, g] == pytest.approx(rho * u[a] * u[b] * u[g], rel=1e-11, abs=1e-15)
 
 
+@pytest.mark.parametrize("order", [3, 2])
 @pytest.mark.parametrize("seed", [3, 4])
-def test_nonequilibrium_hermite_coefficients(oracle, seed):
+def test_nonequilibrium_hermite_coefficients(oracle, seed, order):
     rng = np.random.default_rng(seed)
     u = 0.1 * rng.standard_normal(3)
     pi6 = 1e-2 * rng.standard_normal(6)
     P = np.array([[pi6[0], pi6[3], pi6[4]], [pi6[3], pi6[1], pi6[5]], [pi6[4], pi6[5], pi6[2]]])
     c, w, _ = oracle.lattice()
-    f = np.array([oracle.fneq(i, pi6, u) for i in range(27)])
+    f = np.array([oracle.fneq(i, pi6, u, order) for i in range(27)])
     H2 = _H(oracle, 2)
     H3 = _H(oracle, 3)
     assert abs(f.sum()) < 1e-17
@@ -141,7 +145,7 @@ def test_nonequilibrium_hermite_coefficients(oracle, seed):
     assert np.allclose(np.einsum("i,iab->ab", f, H2), P, rtol=1e-12, atol=1e-17)
     a3 = np.einsum("i,iabg->abg", f, H3)
     for (a, b, g) in itertools.product(range(3), repeat=3):
-        want = 0.0 if len({a, b, g}) == 1 else P[a, b] * u[g] + P[b, g] * u[a] + P[a, g] * u[b]
+        want = 0.0 if (len({a, b, g}) == 1 or order == 2) else P[a, b] * u[g] + P[b, g] * u[a] + P[a, g] * u[b]
         assert a3[a, b, g] == pytest.approx(want, rel=1e-11, abs=1e-15)
 
 

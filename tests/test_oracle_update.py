@@ -18,8 +18,9 @@ import workloads as W
 CS2 = 1.0 / 3.0
 
 
-def test_uniform_equilibrium_is_a_fixed_point(oracle):
-    G = oracle.make_grid(4, 5, 3, 0.7)
+@pytest.mark.parametrize("order", [3, 2])
+def test_uniform_equilibrium_is_a_fixed_point(oracle, order):
+    G = oracle.make_grid(4, 5, 3, 0.7, order=order)
     st = W.rest_state(G.shape)
     st[0] = 1.13
     st[1:4] = np.array([0.07, -0.04, 0.02])[:, None, None, None]
@@ -27,10 +28,11 @@ def test_uniform_equilibrium_is_a_fixed_point(oracle):
     assert np.abs(out - st).max() < 1e-15
 
 
-def test_homogeneous_relaxation_closed_form(oracle):
+@pytest.mark.parametrize("order", [3, 2])
+def test_homogeneous_relaxation_closed_form(oracle, order):
     """Uniform rho, u and Pi: rho and u are kept, Pi -> (1 - omega) Pi."""
     tau = 0.62
-    G = oracle.make_grid(3, 4, 5, tau)
+    G = oracle.make_grid(3, 4, 5, tau, order=order)
     st = W.rest_state(G.shape)
     st[0] = 0.98
     st[1:4] = np.array([0.03, 0.05, -0.02])[:, None, None, None]
@@ -41,8 +43,9 @@ def test_homogeneous_relaxation_closed_form(oracle):
     assert np.abs(out - want).max() < 1e-15
 
 
-def test_conservation_periodic_and_forced(oracle):
-    G = oracle.make_grid(5, 4, 6, 0.55)
+@pytest.mark.parametrize("order", [3, 2])
+def test_conservation_periodic_and_forced(oracle, order):
+    G = oracle.make_grid(5, 4, 6, 0.55, order=order)
     st = W.random_state(G.shape, seed=11)
     r0, _ = oracle.reduce(G, st)
     r1, _ = oracle.reduce(G, oracle.step(G, st))
@@ -101,7 +104,7 @@ def _push_reference(oracle, G, st, g):
         m = st[:, z, y, x]
         gg = g[:, z, y, x] if g is not None else np.array(G.force[:])
         for i in range(27):
-            f = oracle.fpost(i, m, gg, omega)
+            f = oracle.fpost(i, m, gg, omega, G.order)
             X, Y, Z = x + c[i, 0], y + c[i, 1], z + c[i, 2]
             X, Y, Z = X % nx, Y % ny, Z % nz  # wall layers sit inside the array
             if kinds[Z, Y, X] == 1:
@@ -115,9 +118,10 @@ def _push_reference(oracle, G, st, g):
     return out
 
 
+@pytest.mark.parametrize("order", [3, 2])
 @pytest.mark.parametrize("faces", [(0,) * 6, (0, 0, 1, 1, 0, 0), (1, 1, 0, 0, 1, 1)])
-def test_pull_update_matches_population_push(oracle, faces):
-    G = oracle.make_grid(4, 5, 6, 0.66, faces=faces)
+def test_pull_update_matches_population_push(oracle, faces, order):
+    G = oracle.make_grid(4, 5, 6, 0.66, faces=faces, order=order)
     st = W.random_state(G.shape, seed=15)
     g = W.random_force(G.shape, seed=16, amp=1e-4)
     want = _push_reference(oracle, G, st, g)
@@ -154,10 +158,11 @@ def _rotate(st, perm, sign):
     return out
 
 
-def test_cube_symmetry_equivariance(oracle):
+@pytest.mark.parametrize("order", [3, 2])
+def test_cube_symmetry_equivariance(oracle, order):
     """The 48 symmetries of the cube commute with the update (isotropy of the
     Hermite tensors and the lattice), tested on a tiny periodic grid."""
-    G = oracle.make_grid(4, 4, 4, 0.58)
+    G = oracle.make_grid(4, 4, 4, 0.58, order=order)
     st = W.random_state(G.shape, seed=17, u_amp=0.05, pi_amp=3e-3)
     base = oracle.step(G, st)
     worst = 0.0
@@ -169,7 +174,8 @@ def test_cube_symmetry_equivariance(oracle):
     assert worst < 1e-15
 
 
-def test_shear_wave_closed_form_eigenvalue(oracle):
+@pytest.mark.parametrize("order", [3, 2])
+def test_shear_wave_closed_form_eigenvalue(oracle, order):
     """Linear shear mode u_x = A sin(k y), Pi_xy = s A cos(k y): one step is the
     2x2 map [[(2 + cos k)/3, (1-w) sin k], [-sin k / 3, (1-w) cos k]] (derived
     from the update with the D3Q27 weights); its dominant eigenvalue gives the
@@ -181,7 +187,7 @@ def test_shear_wave_closed_form_eigenvalue(oracle):
     D = (1 - om) * (1 + 2 * np.cos(k)) / 3
     lam = (T + np.sqrt(T * T - 4 * D)) / 2
     s = -(np.sin(k) / 3) / (lam - (1 - om) * np.cos(k))
-    G = oracle.make_grid(1, n, 1, tau)
+    G = oracle.make_grid(1, n, 1, tau, order=order)
     y = np.arange(n)
     st = W.rest_state(G.shape)
     st[1, 0, :, 0] = A * np.sin(k * y)
@@ -245,3 +251,18 @@ def test_update_nodes_equals_full_step(oracle):
     idx = np.flatnonzero(kinds == 0)[::3]
     part = oracle.update_nodes(G, st, idx)
     assert np.array_equal(part, full.reshape(10, -1)[:, idx])
+
+
+def test_order_two_drops_third_order_moments(oracle):
+    """The higher-order update differs from the regularised one exactly in the
+    third-order Hermite content: from a uniform moving state with Pi = 0 both
+    keep (rho, u), but their post-collision populations differ by
+    w H3:(rho u u u) / (6 cs6) (Eq. (eqts) minus Eq. (lbequil))."""
+    c, w, _ = oracle.lattice()
+    m = np.array([1.03, 0.05, -0.04, 0.02, 0, 0, 0, 0, 0, 0], dtype=float)
+    rho, u = m[0], m[1:4]
+    for i in range(27):
+        d = oracle.fpost(i, m, np.zeros(3), 1.3, 3) - oracle.fpost(i, m, np.zeros(3), 1.3, 2)
+        cu = c[i] @ u
+        h3uuu = cu ** 3 - 3 * CS2 * cu * (u @ u)
+        assert d == pytest.approx(w[i] * rho * h3uuu / (6 * CS2 ** 3), rel=1e-10, abs=1e-18)
