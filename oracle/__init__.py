@@ -45,6 +45,8 @@ class Grid(ctypes.Structure):
         ("inlet_noise", ctypes.c_double),
         ("seed", ctypes.c_uint64),
         ("order", ctypes.c_int),
+        ("noise_kind", ctypes.c_int),
+        ("tau_z", ctypes.POINTER(ctypes.c_double)),
     ]
 
     @property
@@ -57,9 +59,13 @@ class Grid(ctypes.Structure):
 
 
 def make_grid(nx, ny, nz, tau, faces=(PERIODIC,) * 6, force=(0.0, 0.0, 0.0), inlet_u=(0.0, 0.0, 0.0),
-              inlet_center=(0.0, 0.0), inlet_radius=0.0, inlet_noise=0.0, seed=0, order=3):
+              inlet_center=(0.0, 0.0), inlet_radius=0.0, inlet_noise=0.0, seed=0, order=3, noise_kind=0,
+              tau_z=None):
     """order: 3 = the recursive third-order update (Section 2.2), 2 = the
-    regularised second-order update (Eq. (fullstrcoll))."""
+    regularised second-order update (Eq. (fullstrcoll)).
+    noise_kind: inlet perturbation, 0 uniform in [-1, 1), 1 standard Gaussian.
+    tau_z: optional relaxation time per z plane (nz values; the outlet sponge
+    of Section 3.2); every node relaxes with the value of its own plane."""
     g = Grid()
     g.nx, g.ny, g.nz = nx, ny, nz
     for k in range(6):
@@ -73,6 +79,12 @@ def make_grid(nx, ny, nz, tau, faces=(PERIODIC,) * 6, force=(0.0, 0.0, 0.0), inl
     g.inlet_noise = inlet_noise
     g.seed = seed
     g.order = order
+    g.noise_kind = noise_kind
+    if tau_z is not None:
+        arr = np.ascontiguousarray(tau_z, dtype=np.float64)
+        assert arr.shape == (nz,)
+        g._tau_z = arr  # keeps the buffer alive as long as the grid
+        g.tau_z = arr.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
     return g
 
 
@@ -108,6 +120,8 @@ def _load():
         "or_splitmix64": (ctypes.c_uint64, [ctypes.c_uint64, ctypes.c_uint64]),
         "or_inlet_xi": (ctypes.c_double, [ctypes.c_uint64, ctypes.c_long, ctypes.c_long, ctypes.c_long,
                                           ctypes.c_int]),
+        "or_inlet_gauss": (ctypes.c_double, [ctypes.c_uint64, ctypes.c_long, ctypes.c_long, ctypes.c_long,
+                                             ctypes.c_int]),
         "or_round_fp16": (ctypes.c_double, [ctypes.c_double]),
         "or_round_bf16": (ctypes.c_double, [ctypes.c_double]),
         "or_jvp_step": (ctypes.c_int, [G, _D, _D, _D, _D, ctypes.c_long, _D]),
@@ -247,6 +261,10 @@ def splitmix64(seed, k):
 
 def inlet_xi(seed, t, n, N, a):
     return _load().or_inlet_xi(seed, t, n, N, a)
+
+
+def inlet_gauss(seed, t, n, N, a):
+    return _load().or_inlet_gauss(seed, t, n, N, a)
 
 
 def round_fp16(x):

@@ -90,6 +90,8 @@ typedef struct {
     double inlet_noise; /* relative amplitude of the inlet perturbation */
     uint64_t seed;
     int order; /* Hermite order of the reconstruction: 3 (Section 2.2) or 2 (Eq. (fullstrcoll)) */
+    int noise_kind; /* inlet perturbation: 0 uniform in [-1, 1), 1 standard Gaussian (Section 3.2) */
+    const double *tau_z; /* relaxation time of each z plane (the jet's outlet sponge), or NULL: tau */
 } or_grid;
 
 static int dim(const or_grid *G, int d) { return d == 0 ? G->nx : (d == 1 ? G->ny : G->nz); }
@@ -100,6 +102,14 @@ static void node_coords(const or_grid *G, long n, int x[3])
     x[0] = (int)(n % G->nx);
     x[1] = (int)((n / G->nx) % G->ny);
     x[2] = (int)(n / ((long)G->nx * G->ny));
+}
+
+/* Relaxation frequency omega = 1/tau of node n: the plane's entry of the
+ * sponge profile when one is given (Section 3.2), else the global tau.      */
+static double omega_at(const or_grid *G, long n)
+{
+    if (!G->tau_z) return 1.0 / G->tau;
+    return 1.0 / G->tau_z[n / ((long)G->nx * G->ny)];
 }
 
 static long node_index(const or_grid *G, const int x[3])
@@ -177,6 +187,20 @@ static double inlet_xi(uint64_t seed, long t, long n, long N, int a)
     return ldexp((double)(h >> 40), -24) * 2.0 - 1.0;
 }
 
+/* Standard Gaussian variate for (level t, node n, component a) by the
+ * Box-Muller transform (Box and Muller 1958) of two uniforms drawn from
+ * outputs k1 = 1 + 6 (t N + n) + 2 a and k1 + 1 of the same stream:
+ *   v1 = (top 24 bits of output k1 + 1) 2^-24   in (0, 1]
+ *   v2 = (top 24 bits of output k1 + 1 + 1) 2^-24 in [0, 1)
+ *   xi = sqrt(-2 ln v1) cos(2 pi v2).                                        */
+static double inlet_gauss(uint64_t seed, long t, long n, long N, int a)
+{
+    uint64_t k = 1ULL + 6ULL * ((uint64_t)t * (uint64_t)N + (uint64_t)n) + 2ULL * (uint64_t)a;
+    double v1 = ldexp((double)((splitmix64_at(seed, k) >> 40) + 1), -24);
+    double v2 = ldexp((double)(splitmix64_at(seed, k + 1) >> 40), -24);
+    return sqrt(-2.0 * log(v1)) * cos(6.283185307179586476925286766559 * v2);
+}
+
 /* Imposed velocity of an inlet-disc ghost node at level t (top hat plus the
  * seeded perturbation); returns 0 if the node is not on an inlet disc.      */
 static int inlet_velocity(const or_grid *G, const int x[3], long n, long t, double ub[3])
@@ -194,7 +218,8 @@ static int inlet_velocity(const or_grid *G, const int x[3], long n, long t, doub
         double mag = sqrt(G->inlet_u[0] * G->inlet_u[0] + G->inlet_u[1] * G->inlet_u[1] +
                           G->inlet_u[2] * G->inlet_u[2]);
         for (int a = 0; a < 3; a++)
-            ub[a] = G->inlet_u[a] + G->inlet_noise * mag * inlet_xi(G->seed, t, n, N, a);
+            ub[a] = G->inlet_u[a] + G->inlet_noise * mag *
+                    (G->noise_kind == 1 ? inlet_gauss(G->seed, t, n, N, a) : inlet_xi(G->seed, t, n, N, a));
         return 1;
     }
     return 0;
@@ -381,6 +406,7 @@ int or_num_threads(void) { return omp_get_max_threads(); }
 
 uint64_t or_splitmix64(uint64_t seed, uint64_t k) { return splitmix64_at(seed, k); }
 double or_inlet_xi(uint64_t seed, long t, long n, long N, int a) { return inlet_xi(seed, t, n, N, a); }
+double or_inlet_gauss(uint64_t seed, long t, long n, long N, int a) { return inlet_gauss(seed, t, n, N, a); }
 
 /* ------------------------------------------------------------------ */
 /* Tangent and adjoint of one step (fluid nodes; periodic axes and walls;
@@ -436,7 +462,7 @@ static void adjoint_emit(const or_grid *G, const double *st, const double *gf, l
                          double lm[10], double lg[3])
 {
     const long N = (long)G->nx * G->ny * G->nz;
-    double omega = 1.0 / G->tau;
+    double omega = omega_at(G, s);
     for (int p = 0; p < 13; p++) {
         double complex m[10], g[3];
         for (int q = 0; q < 10; q++) m[q] = st[q * N + s];

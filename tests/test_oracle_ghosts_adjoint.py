@@ -109,10 +109,13 @@ def test_storage_rounding_emulation(oracle):
     assert np.abs(r[1:4] - st[1:4]).max() <= 2.0 ** -11 * 0.03
 
 
+@pytest.mark.parametrize("sponge", [False, True])
 @pytest.mark.parametrize("faces", [(0,) * 6, (0, 0, 1, 1, 0, 0)])
-def test_adjoint_dot_product_identity(oracle, faces):
-    """<lam, J v> = <J^T lam, v> with J v from the complex-step tangent."""
-    G = oracle.make_grid(5, 6, 4, 0.61, faces=faces)
+def test_adjoint_dot_product_identity(oracle, faces, sponge):
+    """<lam, J v> = <J^T lam, v> with J v from the complex-step tangent (also
+    with a relaxation time that varies from plane to plane)."""
+    tau_z = [0.61, 0.7, 0.95, 1.4] if sponge else None
+    G = oracle.make_grid(5, 6, 4, 0.61, faces=faces, tau_z=tau_z)
     st = W.random_state(G.shape, seed=25, u_amp=0.05, pi_amp=2e-3)
     g = W.random_force(G.shape, seed=26, amp=1e-4)
     rng = np.random.default_rng(27)
@@ -188,3 +191,46 @@ def test_uniform_flow_through_inlet_and_outlets_is_a_fixed_point(oracle):
     st[1:4] = U[:, None, None, None]
     st = oracle.ghost_fill(G, st, 0)
     assert np.abs(oracle.run(G, st, 1) - st).max() > 1e-4
+
+
+def test_gaussian_inlet_variates_are_standard_normal(oracle):
+    """The Box-Muller variates of the time-varying Gaussian inlet noise
+    (Section 3.2) follow N(0, 1): moments, the one-sigma mass, a
+    Kolmogorov-Smirnov test, and no correlation between components or
+    between consecutive levels."""
+    from scipy import stats
+    N = 5000
+    xs = np.array([[oracle.inlet_gauss(99, t, n, N, a) for n in range(N) for t in range(8)] for a in range(3)])
+    x = xs.ravel()
+    m = x.size
+    assert abs(x.mean()) < 5.0 / np.sqrt(m)
+    assert abs(x.var() - 1.0) < 5.0 * np.sqrt(2.0 / m)
+    assert abs(stats.kurtosis(x, fisher=False) - 3.0) < 5.0 * np.sqrt(24.0 / m)
+    assert abs((np.abs(x) < 1.0).mean() - 0.682689) < 5.0 * np.sqrt(0.2166 / m)
+    assert stats.kstest(x, "norm").pvalue > 1e-4
+    for a, b in ((0, 1), (0, 2), (1, 2)):
+        assert abs(np.corrcoef(xs[a], xs[b])[0, 1]) < 5.0 / np.sqrt(xs.shape[1])
+    lag = xs[0].reshape(N, 8)
+    assert abs(np.corrcoef(lag[:, :-1].ravel(), lag[:, 1:].ravel())[0, 1]) < 5.0 / np.sqrt(lag[:, 1:].size)
+
+
+def test_gaussian_inlet_ghost_velocity(oracle):
+    """Inlet-disc ghost nodes get u = U + noise |U| xi with the Gaussian xi
+    of their (level, node, component); nodes off the disc get none."""
+    U = (0.0, 0.0, 0.05)
+    G = oracle.make_grid(9, 9, 6, 0.6, faces=(0, 0, 0, 0, 2, 3), inlet_u=U, inlet_center=(4.0, 4.0),
+                         inlet_radius=2.5, inlet_noise=0.02, seed=5, noise_kind=1)
+    st = oracle.ghost_fill(G, W.rest_state(G.shape), 3)
+    kinds = oracle.node_kinds(G)
+    hit = 0
+    for y in range(9):
+        for x in range(9):
+            n = x + 9 * y
+            if (x - 4) ** 2 + (y - 4) ** 2 <= 2.5 ** 2:
+                hit += 1
+                for a in range(3):
+                    want = U[a] + 0.02 * 0.05 * oracle.inlet_gauss(5, 3, n, G.n, a)
+                    assert st[1 + a, 0, y, x] == want
+            else:
+                assert np.all(st[1:4, 0, y, x] == 0.0)
+    assert hit == 21 and kinds[0].max() == 2

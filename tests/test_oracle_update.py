@@ -88,19 +88,20 @@ def test_tau_one_is_a_streamed_equilibrium(oracle):
     assert np.abs(out[1:4] - j / rho).max() < 1e-15
 
 
-def _push_reference(oracle, G, st, g):
+def _push_reference(oracle, G, st, g, tau_z=None):
     """Independent population-push implementation: every node emits its 27
-    post-collision populations along c_i; a population aimed at a solid node is
-    returned to its emitter in the opposite direction; moments are summed from
-    the arrived sets.  Walls/periodic only."""
+    post-collision populations along c_i, relaxed with its own tau (that of
+    its z plane when a profile is given); a population aimed at a solid node
+    is returned to its emitter in the opposite direction; moments are summed
+    from the arrived sets.  Walls/periodic only."""
     c, w, opp = oracle.lattice()
     nz, ny, nx = G.shape
     kinds = oracle.node_kinds(G)
-    omega = 1.0 / G.tau
     fin = np.zeros((27,) + G.shape)
     for z, y, x in itertools.product(range(nz), range(ny), range(nx)):
         if kinds[z, y, x] != 0:
             continue
+        omega = 1.0 / (G.tau if tau_z is None else tau_z[z])
         m = st[:, z, y, x]
         gg = g[:, z, y, x] if g is not None else np.array(G.force[:])
         for i in range(27):
@@ -128,6 +129,31 @@ def test_pull_update_matches_population_push(oracle, faces, order):
     got = oracle.step(G, st, g)
     kinds = oracle.node_kinds(G)
     assert np.abs((got - want)[:, kinds == 0]).max() < 1e-15
+
+
+@pytest.mark.parametrize("faces", [(0,) * 6, (0, 0, 1, 1, 1, 1)])
+def test_relaxation_profile_matches_population_push(oracle, faces):
+    """A relaxation time that varies with z (the jet's outlet sponge,
+    Section 3.2): each population relaxes with the tau of the node that
+    emits it."""
+    tau_z = [0.55, 0.6, 0.72, 0.9, 1.3, 2.0]
+    G = oracle.make_grid(4, 5, 6, 0.66, faces=faces, tau_z=tau_z)
+    st = W.random_state(G.shape, seed=35)
+    g = W.random_force(G.shape, seed=36, amp=1e-4)
+    want = _push_reference(oracle, G, st, g, tau_z)
+    got = oracle.step(G, st, g)
+    kinds = oracle.node_kinds(G)
+    assert np.abs((got - want)[:, kinds == 0]).max() < 1e-15
+    # a constant profile is the scalar tau, bit for bit
+    G1 = oracle.make_grid(4, 5, 6, 0.66, faces=faces, tau_z=[0.66] * 6)
+    G0 = oracle.make_grid(4, 5, 6, 0.66, faces=faces)
+    assert np.array_equal(oracle.step(G1, st, g), oracle.step(G0, st, g))
+    # mass and momentum stay conserved (periodic box)
+    if faces == (0,) * 6:
+        r0, _ = oracle.reduce(G, st)
+        r1, _ = oracle.reduce(G, got)
+        assert abs(r1[0] - r0[0]) < 1e-12 * r0[0]
+        assert np.allclose(r1[1:4] - r0[1:4], (st[0] * g).sum(axis=(1, 2, 3)), rtol=0, atol=1e-15)
 
 
 def _rotate(st, perm, sign):
