@@ -66,13 +66,19 @@ def time_steps(solver, steps, warmup):
     return e0.elapsed_time(e1), wall
 
 
-def _solver(case, storage=0, kernel=0):
+def _solver(case, storage=0, kernel=0, order=3):
     import numpy as np
+    import workloads as W
     from paper_2401_17074_amd import Solver
     f32 = lambda v: float(np.float32(v))  # noqa: E731
-    return Solver(case.nx, case.ny, case.nz, f32(case.tau), force=[f32(v) for v in case.force], faces=case.faces,
-                  storage=storage, inlet_u=case.inlet_u, inlet_center=case.inlet_center,
-                  inlet_radius=case.inlet_radius, inlet_noise=case.inlet_noise, seed=case.seed, kernel=kernel)
+    s = Solver(case.nx, case.ny, case.nz, f32(case.tau), force=[f32(v) for v in case.force], faces=case.faces,
+               storage=storage, inlet_u=case.inlet_u, inlet_center=case.inlet_center,
+               inlet_radius=case.inlet_radius, inlet_noise=case.inlet_noise, seed=case.seed, kernel=kernel,
+               order=order, inlet_noise_kind=case.noise_kind)
+    prof = W.tau_profile(case)
+    if prof is not None:
+        s.set_relaxation_profile([f32(v) for v in prof])
+    return s
 
 
 def _device_state(st64):
@@ -194,13 +200,112 @@ def load_traffic(kernel_name, case_name, storage):
     return rec.get("hbm_bytes_per_launch")
 
 
+def _counter_mean(folder, counter, name_part):
+    import csv
+    import glob
+    files = glob.glob(os.path.join(folder, "**", "*counter_collection.csv"), recursive=True)
+    vals = []
+    for f in files:
+        for r in csv.DictReader(open(f)):
+            if r["Counter_Name"] == counter and name_part in r["Kernel_Name"]:
+                vals.append(float(r["Counter_Value"]))
+    if not vals:
+        raise SystemExit("no %s samples for %s in %s" % (counter, name_part, folder))
+    return sum(vals) / len(vals), len(vals)
+
+
+def summarize_pmc(args):
+    """HBM bytes per launch of the update kernel from FETCH_SIZE / WRITE_SIZE
+    (KiB per dispatch), each scaled by what the same counter reads for a plain
+    copy of known size (bench.py --copy-calibration, 1 GiB read + 1 GiB written
+    per launch)."""
+    fdir, wdir, cfdir, cwdir = args.summarize_pmc
+    kname = ("update_tiled", "update_direct", "push")[args.kernel]
+    fetch, nf = _counter_mean(fdir, "FETCH_SIZE", kname + "_kernel")
+    write, nw = _counter_mean(wdir, "WRITE_SIZE", kname + "_kernel")
+    cfetch, _ = _counter_mean(cfdir, "FETCH_SIZE", "copyBuffer")
+    cwrite, _ = _counter_mean(cwdir, "WRITE_SIZE", "copyBuffer")
+    copy_kib = 1024.0 * 1024.0  # 1 GiB each way
+    ffac, wfac = copy_kib / cfetch, copy_kib / cwrite
+    import workloads as W
+    case, _ = WORKLOADS[args.workload](W)
+    algo = algorithmic_bytes(case, 0)
+    rec = {"kernel": kname, "workload": case.name, "storage": 0, "source_hash": _source_hash(),
+           "fetch_kib_per_dispatch": fetch, "write_kib_per_dispatch": write, "dispatches": [nf, nw],
+           "copy_fetch_factor": ffac, "copy_write_factor": wfac,
+           "hbm_bytes_per_launch": (fetch * ffac + write * wfac) * 1024.0,
+           "algorithmic_bytes_per_launch": algo}
+    rec["traffic_over_algorithmic"] = rec["hbm_bytes_per_launch"] / algo
+    path = os.path.join(ROOT, "profiles", "pmc_%s_%s.json" % (kname, case.name))
+    os.makedirs(os.path.dirname(path), exist_ok=True)
+    json.dump(rec, open(path, "w"), indent=1)
+    print(json.dumps(rec))
+
+
 WORKLOADS = {
     "channel": lambda W: (lambda c: (c, W.channel_state(c)))(W.channel_case()),
     "channel512": lambda W: (lambda c: (c, W.channel_state(c)))(W.channel_case(nx=512, ny=256, nz=256)),
     "jet": lambda W: (lambda c: (c, W.jet_state(c)))(W.jet_case()),
+    "paper_jet": lambda W: (lambda c: (c, W.jet_state(c)))(W.paper_jet_case()),
     "cube512": lambda W: (lambda c: (c, W.tgv_state(c.nx, 0.01)))(W.tgv_case(n=512)),
     "tgv32": lambda W: (lambda c: (c, W.tgv_state(c.nx, 0.01)))(W.tgv_case()),
 }
+
+
+def measure_workloads(names, steps, warmup, kernel):
+    """MLUPS and HBM roofline fraction of the update kernel on the other
+    synthetic workloads (same bytes-per-node accounting as the headline)."""
+    import workloads as W
+    out = {}
+    for name in names:
+        case, st64 = WORKLOADS[name](W)
+        s = _solver(case, 0, kernel)
+        s.set_state(_device_state(st64))
+        ms, _ = time_steps(s, steps, warmup)
+        kms, _ = s.step_timed(steps)
+        s.close()
+        gbs = algorithmic_bytes(case, 0) / (kms * 1e-3 / steps) / 1e9
+        out[case.name] = {"mlups": round(case.nodes * steps / (ms * 1e-3) / 1e6, 1),
+                          "kernel_ms": round(kms / steps, 5), "hbm_gbs": round(gbs, 1),
+                          "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
+    return {"steps": steps, **out}
+
+
+def measure_order_variants(case, st, steps, warmup, kernel):
+    """Third-order update against the regularised second-order one
+    (Eq. (fullstrcoll)) on the same workload: the cost of the high-order
+    reconstruction."""
+    out = {}
+    for order in (3, 2):
+        s = _solver(case, 0, kernel, order)
+        s.set_state(st)
+        ms, _ = time_steps(s, steps, warmup)
+        kms, _ = s.step_timed(steps)
+        s.close()
+        out["order%d" % order] = {"mlups": round(case.nodes * steps / (ms * 1e-3) / 1e6, 1),
+                                  "kernel_ms": round(kms / steps, 5)}
+    return {"workload": case.name, "steps": steps, **out}
+
+
+def measure_layout_variants(case, st, steps, warmup):
+    """The moment-only layout (tiled kernel) against the paper's own layout,
+    one population set plus the moments (push pass + moment pass), on the
+    same workload.  Algorithmic bytes per node: 10 + 10 stored values against
+    10 + 27 + 27 + 10."""
+    out = {}
+    fl = _fluid_nodes(case)
+    for kernel, name, vals in ((0, "moments_only", 10 * case.nodes + 10 * fl),
+                               (2, "populations_plus_moments", 37 * case.nodes + 37 * fl)):
+        s = _solver(case, 0, kernel)
+        s.set_state(st)
+        ms, _ = time_steps(s, steps, warmup)
+        kms, _ = s.step_timed(steps)
+        s.close()
+        out[name] = {"mlups": round(case.nodes * steps / (ms * 1e-3) / 1e6, 1),
+                     "update_ms": round(kms / steps, 5),
+                     "algorithmic_bytes_per_step": 4 * vals,
+                     "hbm_gbs": round(4 * vals / (kms * 1e-3 / steps) / 1e9, 1)}
+    return {"workload": case.name, "steps": steps, **out}
 
 
 def main():
@@ -208,14 +313,19 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--kernel", type=int, default=0, help="0 tiled (default), 1 direct")
+    ap.add_argument("--kernel", type=int, default=0, help="0 tiled (default), 1 direct, 2 population layout")
     ap.add_argument("--workload", default="channel", choices=sorted(WORKLOADS),
                     help="timed workload (default: the 384x192x192 channel)")
     ap.add_argument("--quick", action="store_true", help="only the timed workload (for profiling)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB 20 times (HBM counter calibration)")
+    ap.add_argument("--summarize-pmc", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "COPY_FETCH_DIR", "COPY_WRITE_DIR"),
+                    help="turn four rocprofv3 --pmc output folders into profiles/pmc_<kernel>_<workload>.json")
     args = ap.parse_args()
+    if args.summarize_pmc:
+        summarize_pmc(args)
+        return
     if args.copy_calibration:
         import torch
         n = args.copy_calibration * (1 << 20) // 4
@@ -240,11 +350,15 @@ def main():
     s = _solver(case, 0, args.kernel)
     s.set_state(_device_state(st64))
     ms, wall = time_steps(s, args.steps, args.warmup)
+    # the dominant kernel alone: HIP events around each of its launches, on
+    # the stream it runs on (the library's; the default stream here)
+    n_timed = min(args.steps, 200)
+    kms, aux_ms = s.step_timed(n_timed)
     _, rc = s.reduce(check=False)
     s.close()
     mlups = case.nodes * args.steps / (ms * 1e-3) / 1e6
-    kname = "update_tiled" if args.kernel == 0 else "update_direct"
-    per_launch_s = ms * 1e-3 / args.steps
+    kname = ("update_tiled", "update_direct", "push")[args.kernel]
+    per_launch_s = kms * 1e-3 / n_timed
     algo = algorithmic_bytes(case, 0)
     achieved = algo / per_launch_s / 1e9
     rec = {
@@ -265,11 +379,15 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": load_traffic(kname, case.name, 0),
-                     "algorithmic_bytes_per_launch": algo, "avg_launch_ms": round(per_launch_s * 1e3, 5)},
+                     "algorithmic_bytes_per_launch": algo, "avg_launch_ms": round(per_launch_s * 1e3, 5),
+                     "kernel": kname, "aux_ms_per_step": round(aux_ms / n_timed, 5)},
         "wall_s": round(wall, 3),
     }
     if not args.quick:
         rec["storage_variants"] = measure_storage_variants(200, 10, args.kernel)
+        rec["order_variants"] = measure_order_variants(case, _device_state(st64), 200, 10, args.kernel)
+        rec["layout_variants"] = measure_layout_variants(case, _device_state(st64), 200, 10)
+        rec["other_workloads"] = measure_workloads(["cube512", "jet", "paper_jet"], 100, 5, args.kernel)
         rec["adjoint"] = measure_adjoint(args.kernel)
         if not args.no_cpu:
             rec["cpu_baseline"] = cpu_baseline(case, st64)

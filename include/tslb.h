@@ -62,10 +62,9 @@ enum {
  *  inlet_*         for TSLB_INLET faces: nodes of the face layer inside the
  *                  disc |(t1, t2) - inlet_center| <= inlet_radius (t1 < t2 are
  *                  the two transverse axes in x, y, z order) get
- *                  u = inlet_u + inlet_noise * |inlet_u| * xi, with xi uniform
- *                  in [-1, 1) per component, drawn from the SplitMix64 stream
- *                  of `seed` at position k = 1 + 3 (t N + n) + component for
- *                  level t and node n; rho and Pi^neq come from the interior
+ *                  u = inlet_u + inlet_noise * |inlet_u| * xi per component,
+ *                  xi drawn afresh at every level t from the SplitMix64 stream
+ *                  of `seed` (see inlet_noise_kind); rho and Pi^neq come from the interior
  *                  neighbour.  The rest of an inlet face behaves as an outlet
  *                  (all ten moments copied from the interior neighbour).
  *  storage         TSLB_FP32 / TSLB_FP16 / TSLB_BF16 for the stored moments.
@@ -74,7 +73,20 @@ enum {
  *                  0 selects the default for the storage kind (1 for FP32 and
  *                  BF16; 2^12, 2^12, 2^16 for FP16, which keeps |rho - 1| and
  *                  |u| below 16 and |Pi| below 1 clear of overflow and small
- *                  values clear of subnormals).  Ignored for FP32.            */
+ *                  values clear of subnormals).  Ignored for FP32.
+ *  order           Hermite order of the rebuilt populations: 3 (or 0, the
+ *                  default) is the third-order equilibrium plus the recursive
+ *                  non-equilibrium part of Section 2.2; 2 is the regularised
+ *                  second-order collision of Eq. (fullstrcoll) (equilibrium of
+ *                  Eq. (lbequil), non-equilibrium part projected on H2 only).
+ *                  The adjoint and rollout calls need order 3.
+ *  inlet_noise_kind 0: xi uniform in [-1, 1), the top 24 bits of output
+ *                  k = 1 + 3 (t N + n) + component (node n, level t) mapped
+ *                  to 2 (h >> 40) 2^-24 - 1.  1: xi standard Gaussian (the
+ *                  time-varying Gaussian inflow noise of Section 3.2), the
+ *                  Box-Muller transform sqrt(-2 ln v1) cos(2 pi v2) of
+ *                  v1 = ((h1 >> 40) + 1) 2^-24 and v2 = (h2 >> 40) 2^-24 from
+ *                  outputs k1 = 1 + 6 (t N + n) + 2 component and k1 + 1.   */
 typedef struct {
     int face[6];
     float inlet_u[3];
@@ -84,6 +96,8 @@ typedef struct {
     uint64_t seed;
     int storage;
     float scale[3];
+    int order;
+    int inlet_noise_kind;
 } tslb_bc;
 
 /* Create a solver on an nx*ny*nz grid (Section 2.2 update, D3Q27 only).
@@ -119,9 +133,26 @@ int tslb_get_moments(tslb_handle h, float *rho, float *u, float *pineq, int flag
  * uniform force given at creation.                                          */
 int tslb_set_force_field(tslb_handle h, const float *g, void *stream);
 
+/* Relaxation time per z plane: tau_z holds nz values (host memory, each
+ * > 1/2), copied into the handle; every node then relaxes with the value of
+ * its own plane, in the update and in the adjoint.  This carries the outlet
+ * sponge of the jet benchmark (Section 3.2), where the viscosity grows
+ * towards the outflow face.  NULL returns to the uniform tau of creation.
+ * Synchronises the stream.  Errors: TSLB_E_INVALID for a value <= 1/2 or not
+ * finite (the profile is then unchanged), TSLB_E_NOMEM.                     */
+int tslb_set_relaxation_profile(tslb_handle h, const float *tau_z, void *stream);
+
 /* Advance nsteps time steps (Section 2.2 update, then the ghost refill of
  * Section 2.3 for the new level).  Asynchronous.  nsteps >= 0.               */
 int tslb_step(tslb_handle h, int nsteps, void *stream);
+
+/* tslb_step with per-launch timing, for profiling: HIP events recorded on
+ * `stream` around every launch give ms[0] = summed device time of the main
+ * update kernel launches and ms[1] = summed time of the per-step auxiliary
+ * launches (wall fix-up, ghost refill).  Synchronises the stream.  The
+ * events add a few microseconds between launches, so tslb_step is the one to
+ * time whole runs with.  1 <= nsteps <= 100000.                             */
+int tslb_step_timed(tslb_handle h, int nsteps, double ms[2], void *stream);
 
 /* Current level t (steps taken since creation, or the last tslb_set_time). */
 int64_t tslb_get_time(tslb_handle h);
@@ -173,9 +204,16 @@ int tslb_rollout_forward(tslb_handle h, int nsteps, int every, void *ws, size_t 
 int tslb_rollout_backward(tslb_handle h, int nsteps, int every, void *ws, size_t ws_bytes, float *lam,
                           float *dg_accum, void *stream);
 
-/* Kernel selection for the update: 0 = the LDS-tiled z-marching kernel
- * (default), 1 = the direct one-thread-per-node kernel.  Both compute the
- * same update; the second exists for cross-checks.                          */
+/* Kernel selection for the update and the adjoint step:
+ *  0  the LDS-tiled z-marching kernels (default);
+ *  1  the direct one-thread-per-node kernels (cross-checks);
+ *  2  the population layout of the paper's own GPU code (the memory-footprint
+ *     remark of Section 2.2): a push pass writes every node's 27 populations
+ *     into one population set, a second pass sums them into the moments.
+ *     Allocates 27 N floats on first selection (kept until tslb_destroy;
+ *     TSLB_E_NOMEM if that fails, the variant then stays unchanged); the
+ *     adjoint step uses the tiled kernel.
+ * All compute the same update up to FP32 summation order.                   */
 int tslb_set_kernel(tslb_handle h, int variant);
 
 /* Message of the last failed call on this thread ("" if none). */

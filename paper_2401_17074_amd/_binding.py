@@ -35,6 +35,8 @@ class tslb_bc(ctypes.Structure):
         ("seed", ctypes.c_uint64),
         ("storage", ctypes.c_int),
         ("scale", ctypes.c_float * 3),
+        ("order", ctypes.c_int),
+        ("inlet_noise_kind", ctypes.c_int),
     ]
 
 
@@ -45,6 +47,8 @@ SIGNATURES = {
     "tslb_get_moments": (_i, [_vp, _vp, _vp, _vp, _i, _vp]),
     "tslb_set_force_field": (_i, [_vp, _vp, _vp]),
     "tslb_step": (_i, [_vp, _i, _vp]),
+    "tslb_set_relaxation_profile": (_i, [_vp, _fp, _vp]),
+    "tslb_step_timed": (_i, [_vp, _i, ctypes.POINTER(ctypes.c_double), _vp]),
     "tslb_get_time": (_i64, [_vp]),
     "tslb_set_time": (_i, [_vp, _i64]),
     "tslb_reduce": (_i, [_vp, ctypes.POINTER(_d), _vp]),
@@ -101,7 +105,7 @@ def _stream(stream):
 
 
 def make_bc(faces=(0,) * 6, inlet_u=(0.0, 0.0, 0.0), inlet_center=(0.0, 0.0), inlet_radius=0.0, inlet_noise=0.0,
-            seed=0, storage=TSLB_FP32, scale=(0.0, 0.0, 0.0)):
+            seed=0, storage=TSLB_FP32, scale=(0.0, 0.0, 0.0), order=3, inlet_noise_kind=0):
     b = tslb_bc()
     for k in range(6):
         b.face[k] = faces[k]
@@ -113,6 +117,8 @@ def make_bc(faces=(0,) * 6, inlet_u=(0.0, 0.0, 0.0), inlet_center=(0.0, 0.0), in
     b.inlet_noise = inlet_noise
     b.seed = seed
     b.storage = storage
+    b.order = order
+    b.inlet_noise_kind = inlet_noise_kind
     return b
 
 
@@ -142,6 +148,18 @@ def tslb_set_force_field(h, g, stream=None):
 
 def tslb_step(h, nsteps, stream=None):
     return _check(lib.tslb_step(h, nsteps, _stream(stream)))
+
+
+def tslb_set_relaxation_profile(h, tau_z, stream=None):
+    """tau_z: sequence of nz floats (host), or None for the uniform tau."""
+    arr = None if tau_z is None else (ctypes.c_float * len(tau_z))(*[float(v) for v in tau_z])
+    return _check(lib.tslb_set_relaxation_profile(h, arr, _stream(stream)))
+
+
+def tslb_step_timed(h, nsteps, stream=None):
+    ms = (ctypes.c_double * 2)()
+    _check(lib.tslb_step_timed(h, nsteps, ms, _stream(stream)))
+    return ms[0], ms[1]
 
 
 def tslb_get_time(h):

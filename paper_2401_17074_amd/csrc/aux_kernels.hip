@@ -63,10 +63,19 @@ __global__ void ghost_fill_kernel(typename S::T* __restrict__ st, StepParams p, 
         const int e1 = e == 0 ? 1 : 0, e2 = e == 2 ? 1 : 2;
         const float r1 = (float)c[e1] - q.center[0], r2 = (float)c[e2] - q.center[1];
         if (r1 * r1 + r2 * r2 > q.radius2) continue;
+        const uint64_t tn = (uint64_t)t * (uint64_t)g.N + (uint64_t)n;
         for (int a = 0; a < 3; ++a) {
-            const uint64_t k = 1ull + 3ull * ((uint64_t)t * (uint64_t)g.N + (uint64_t)n) + (uint64_t)a;
-            const uint64_t h = splitmix64(q.seed, k);
-            const float xi = (float)(h >> 40) * 0x1.0p-24f * 2.0f - 1.0f;
+            float xi;
+            if (q.noise_kind == 1) {
+                // Box-Muller: sqrt(-2 ln v1) cos(2 pi v2), v1 in (0, 1], v2 in [0, 1)
+                const uint64_t k = 1ull + 6ull * tn + 2ull * (uint64_t)a;
+                const float v1 = (float)((splitmix64(q.seed, k) >> 40) + 1) * 0x1.0p-24f;
+                const float v2 = (float)(splitmix64(q.seed, k + 1) >> 40) * 0x1.0p-24f;
+                xi = sqrtf(-2.0f * logf(v1)) * cospif(2.0f * v2);
+            } else {
+                const uint64_t h = splitmix64(q.seed, 1ull + 3ull * tn + (uint64_t)a);
+                xi = (float)(h >> 40) * 0x1.0p-24f * 2.0f - 1.0f;
+            }
             st[(1 + a) * g.N + n] = S::store(fmaf(q.amp, xi, q.u[a]), p.scale[1]);
         }
         break;
@@ -275,6 +284,7 @@ __global__ void __launch_bounds__(256) adjoint_step_kernel(const float* __restri
 #pragma unroll
     for (int a = 0; a < 3; ++a) gg[a] = p.gfield ? p.gfield[a * g.N + n] : p.force[a];
     const NodeTerms t = node_terms(m, gg);
+    const float omo = omo_at(p, z);
     float acc[13];
 #pragma unroll
     for (int k = 0; k < 13; ++k) acc[k] = 0.0f;
@@ -293,7 +303,7 @@ __global__ void __launch_bounds__(256) adjoint_step_kernel(const float* __restri
             const float rho1 = 1.0f + st1[d];
 #pragma unroll
             for (int a = 0; a < 3; ++a) u1[a] = st1[(1 + a) * g.N + d];
-            emit_adjoint<I>(t, p.one_minus_omega, arrival_adjoint<I>(l, rho1, u1), acc);
+            emit_adjoint<I>(t, omo, arrival_adjoint<I>(l, rho1, u1), acc);
         }
         // upstream node y - c_I solid: y's own population 26 - I came back as I
         int ux = x - X, uy = y - Y, uz = z - Z;
@@ -307,7 +317,7 @@ __global__ void __launch_bounds__(256) adjoint_step_kernel(const float* __restri
             const float rho1 = 1.0f + st1[n];
 #pragma unroll
             for (int a = 0; a < 3; ++a) u1[a] = st1[(1 + a) * g.N + n];
-            emit_adjoint<26 - I>(t, p.one_minus_omega, arrival_adjoint<I>(l, rho1, u1), acc);
+            emit_adjoint<26 - I>(t, omo, arrival_adjoint<I>(l, rho1, u1), acc);
         }
     });
 #pragma unroll

@@ -7,8 +7,10 @@
 #include <string.h>
 
 #include <new>
+#include <vector>
 
 #include "../../include/tslb.h"
+
 #include "tslb_internal.h"
 
 using namespace tslb;
@@ -36,13 +38,20 @@ inline hipStream_t S(void* s) { return (hipStream_t)s; }
 
 inline bool ghost_kind(int k) { return k == TSLB_INLET || k == TSLB_OUTLET; }
 
-hipError_t run_update(tslb_ctx* h, const void* in, void* out, hipStream_t s) {
-    if (h->kernel == 0) {
-        hipError_t e = launch_update_tiled(h->storage, in, out, h->p, s);
-        if (e != hipSuccess) return e;
-        return launch_wall_fixup(h->storage, in, out, h->p, s);
+// The update proper (without the wall fix-up pass of the tiled kernel).
+hipError_t run_main_update(tslb_ctx* h, const void* in, void* out, hipStream_t s) {
+    switch (h->kernel) {
+    case 0: return launch_update_tiled(h->storage, in, out, h->p, s);
+    case 1: return launch_update_direct(h->storage, in, out, h->p, s);
+    case 2: return launch_update_poplayout(h->storage, in, out, h->pop, h->p, s);
     }
-    return launch_update_direct(h->storage, in, out, h->p, s);
+    return hipErrorInvalidValue;
+}
+
+hipError_t run_update(tslb_ctx* h, const void* in, void* out, hipStream_t s) {
+    hipError_t e = run_main_update(h, in, out, s);
+    if (e != hipSuccess || h->kernel != 0) return e;
+    return launch_wall_fixup(h->storage, in, out, h->p, s);
 }
 
 // Make `dev` current for the duration of a call.
@@ -108,6 +117,10 @@ int tslb_create(int nx, int ny, int nz, int lattice, float tau, const float forc
     }
     if (!(b.inlet_radius >= 0.0f) || !(b.inlet_noise >= 0.0f))
         return fail(TSLB_E_INVALID, "inlet radius and noise must be >= 0");
+    if (b.order == 0) b.order = 3;
+    if (b.order != 2 && b.order != 3) return fail(TSLB_E_INVALID, "Hermite order %d is not 2 or 3", b.order);
+    if (b.inlet_noise_kind != 0 && b.inlet_noise_kind != 1)
+        return fail(TSLB_E_INVALID, "inlet noise kind %d is not 0 or 1", b.inlet_noise_kind);
 
     tslb_ctx* h = new (std::nothrow) tslb_ctx;
     if (!h) return fail(TSLB_E_NOMEM, "host allocation failed");
@@ -127,6 +140,7 @@ int tslb_create(int nx, int ny, int nz, int lattice, float tau, const float forc
     }
     g.N = (long long)nx * ny * nz;
     h->p.one_minus_omega = (float)(1.0 - 1.0 / (double)tau);
+    h->p.order = b.order;
     for (int a = 0; a < 3; ++a) h->p.force[a] = force ? force[a] : 0.0f;
     h->p.gfield = nullptr;
     for (int k = 0; k < 3; ++k) {
@@ -142,6 +156,7 @@ int tslb_create(int nx, int ny, int nz, int lattice, float tau, const float forc
     h->inlet.radius2 = b.inlet_radius * b.inlet_radius;
     h->inlet.amp = (float)((double)b.inlet_noise * umag);
     h->inlet.seed = b.seed;
+    h->inlet.noise_kind = b.inlet_noise_kind;
     h->has_ghosts = (g.lo_ghost | g.hi_ghost) != 0;
     // layers next to wall faces (raw sums of the tiled update, fix-up pass)
     h->p.wall_nodes = 0;
@@ -186,13 +201,23 @@ int tslb_destroy(tslb_handle h) {
     (void)hipFree(h->red_partials);
     (void)hipFree(h->red_out);
     (void)hipFree(h->p.wall_side);
+    (void)hipFree(h->pop);
+    (void)hipFree(h->omo_z);
     delete h;
     return TSLB_OK;
 }
 
 int tslb_set_kernel(tslb_handle h, int variant) {
     if (!h) return fail(TSLB_E_INVALID, "NULL handle");
-    if (variant < 0 || variant > 1) return fail(TSLB_E_INVALID, "kernel variant %d out of range", variant);
+    if (variant < 0 || variant > 2) return fail(TSLB_E_INVALID, "kernel variant %d out of range", variant);
+    if (variant == 2 && !h->pop) {
+        DeviceGuard dg(h->device);
+        const size_t bytes = sizeof(float) * 27 * (size_t)h->p.geo.N;
+        if (hipMalloc((void**)&h->pop, bytes) != hipSuccess) {
+            h->pop = nullptr;
+            return fail(TSLB_E_NOMEM, "population array of %zu bytes", bytes);
+        }
+    }
     h->kernel = variant;
     return TSLB_OK;
 }
@@ -258,6 +283,31 @@ int tslb_set_force_field(tslb_handle h, const float* g, void* stream) {
     return TSLB_OK;
 }
 
+int tslb_set_relaxation_profile(tslb_handle h, const float* tau_z, void* stream) {
+    if (!h) return fail(TSLB_E_INVALID, "NULL handle");
+    if (!tau_z) {
+        h->p.omo_z = nullptr;
+        return TSLB_OK;
+    }
+    const int nz = h->p.geo.n[2];
+    std::vector<float> omo((size_t)nz);
+    for (int z = 0; z < nz; ++z) {
+        const float t = tau_z[z];
+        if (!(t > 0.5f) || !isfinite(t))
+            return fail(TSLB_E_INVALID, "tau_z[%d] = %g must be finite and exceed 1/2", z, (double)t);
+        omo[(size_t)z] = (float)(1.0 - 1.0 / (double)t);
+    }
+    DeviceGuard dg(h->device);
+    if (!h->omo_z && hipMalloc((void**)&h->omo_z, sizeof(float) * (size_t)nz) != hipSuccess) {
+        h->omo_z = nullptr;
+        return fail(TSLB_E_NOMEM, "relaxation profile allocation failed");
+    }
+    HIP_TRY(hipMemcpyAsync(h->omo_z, omo.data(), sizeof(float) * (size_t)nz, hipMemcpyHostToDevice, S(stream)));
+    HIP_TRY(hipStreamSynchronize(S(stream)));
+    h->p.omo_z = h->omo_z;
+    return TSLB_OK;
+}
+
 int tslb_step(tslb_handle h, int nsteps, void* stream) {
     if (!h) return fail(TSLB_E_INVALID, "NULL handle");
     if (nsteps < 0) return fail(TSLB_E_INVALID, "nsteps must be >= 0");
@@ -273,6 +323,56 @@ int tslb_step(tslb_handle h, int nsteps, void* stream) {
         if (rc) return rc;
     }
     return TSLB_OK;
+}
+
+int tslb_step_timed(tslb_handle h, int nsteps, double ms[2], void* stream) {
+    if (!h || !ms) return fail(TSLB_E_INVALID, "NULL handle or output");
+    if (nsteps < 1 || nsteps > 100000) return fail(TSLB_E_INVALID, "nsteps must be in [1, 100000]");
+    DeviceGuard dg(h->device);
+    hipStream_t s = S(stream);
+    std::vector<hipEvent_t> ev(3 * (size_t)nsteps, nullptr);
+    int rc = TSLB_OK;
+    for (auto& e : ev)
+        if (hipEventCreate(&e) != hipSuccess) {
+            e = nullptr;
+            rc = fail(TSLB_E_HIP, "hipEventCreate failed");
+            break;
+        }
+    for (int k = 0; rc == TSLB_OK && k < nsteps; ++k) {
+        void* in = h->buf[h->cur];
+        void* out = h->buf[1 - h->cur];
+        hipError_t e = hipEventRecord(ev[3 * k], s);
+        if (e == hipSuccess) e = run_main_update(h, in, out, s);
+        if (e == hipSuccess) e = hipEventRecord(ev[3 * k + 1], s);
+        if (e == hipSuccess && h->kernel == 0) e = launch_wall_fixup(h->storage, in, out, h->p, s);
+        if (e != hipSuccess) {
+            rc = fail(TSLB_E_HIP, "timed step: %s", hipGetErrorString(e));
+            break;
+        }
+        h->cur = 1 - h->cur;
+        h->t += 1;
+        rc = fill_ghosts(h, out, s);
+        if (rc == TSLB_OK && hipEventRecord(ev[3 * k + 2], s) != hipSuccess) rc = fail(TSLB_E_HIP, "hipEventRecord failed");
+    }
+    if (rc == TSLB_OK) {
+        if (hipStreamSynchronize(s) != hipSuccess) rc = fail(TSLB_E_HIP, "hipStreamSynchronize failed");
+    }
+    double main_ms = 0.0, aux_ms = 0.0;
+    for (int k = 0; rc == TSLB_OK && k < nsteps; ++k) {
+        float a = 0.f, b = 0.f;
+        if (hipEventElapsedTime(&a, ev[3 * k], ev[3 * k + 1]) != hipSuccess ||
+            hipEventElapsedTime(&b, ev[3 * k + 1], ev[3 * k + 2]) != hipSuccess)
+            rc = fail(TSLB_E_HIP, "hipEventElapsedTime failed");
+        main_ms += a;
+        aux_ms += b;
+    }
+    for (auto e : ev)
+        if (e) (void)hipEventDestroy(e);
+    if (rc == TSLB_OK) {
+        ms[0] = main_ms;
+        ms[1] = aux_ms;
+    }
+    return rc;
 }
 
 int64_t tslb_get_time(tslb_handle h) { return h ? h->t : -1; }
@@ -328,9 +428,14 @@ int tslb_adjoint_step(tslb_handle h, const void* state_t, const void* state_t1, 
     if (lam_t == lam_t1) return fail(TSLB_E_INVALID, "lam_t may not alias lam_t1");
     if (h->storage != TSLB_FP32) return fail(TSLB_E_UNSUPPORTED, "the adjoint needs FP32 storage");
     if (h->has_ghosts) return fail(TSLB_E_UNSUPPORTED, "the adjoint does not differentiate inlet/outlet ghosts");
+    if (h->p.order != 3) return fail(TSLB_E_UNSUPPORTED, "the adjoint differentiates the third-order update only");
     DeviceGuard dg(h->device);
-    HIP_TRY(launch_adjoint_step((const float*)state_t, (const float*)state_t1, lam_t1, lam_t, dg_accum, h->p,
-                                S(stream)));
+    if (h->kernel != 1)
+        HIP_TRY(launch_adjoint_tiled((const float*)state_t, (const float*)state_t1, lam_t1, lam_t, dg_accum, h->p,
+                                     S(stream)));
+    else
+        HIP_TRY(launch_adjoint_step((const float*)state_t, (const float*)state_t1, lam_t1, lam_t, dg_accum, h->p,
+                                    S(stream)));
     return TSLB_OK;
 }
 
@@ -344,6 +449,7 @@ size_t tslb_rollout_workspace_bytes(tslb_handle h, int nsteps, int every) {
 int tslb_rollout_forward(tslb_handle h, int nsteps, int every, void* ws, size_t ws_bytes, void* stream) {
     if (!h || !ws || nsteps < 1 || every < 1) return fail(TSLB_E_INVALID, "bad rollout arguments");
     if (ws_bytes < tslb_rollout_workspace_bytes(h, nsteps, every)) return fail(TSLB_E_INVALID, "workspace too small");
+    if (h->p.order != 3) return fail(TSLB_E_UNSUPPORTED, "the adjoint differentiates the third-order update only");
     const size_t sb = tslb_state_bytes(h);
     char* ck = (char*)ws;
     for (int s0 = 0, seg = 0; s0 < nsteps; s0 += every, ++seg) {
@@ -359,6 +465,7 @@ int tslb_rollout_backward(tslb_handle h, int nsteps, int every, void* ws, size_t
                           float* dg_accum, void* stream) {
     if (!h || !ws || !lam || nsteps < 1 || every < 1) return fail(TSLB_E_INVALID, "bad rollout arguments");
     if (ws_bytes < tslb_rollout_workspace_bytes(h, nsteps, every)) return fail(TSLB_E_INVALID, "workspace too small");
+    if (h->p.order != 3) return fail(TSLB_E_UNSUPPORTED, "the adjoint differentiates the third-order update only");
     DeviceGuard dg(h->device);
     hipStream_t s = S(stream);
     const size_t sb = tslb_state_bytes(h);

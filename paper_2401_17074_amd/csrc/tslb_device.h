@@ -157,8 +157,9 @@ __device__ __forceinline__ NodeTerms node_terms(const float m[10], const float g
 }
 
 // Scaled deviation G = 216 w(c) P(c) of the population emitted along
-// velocity I (compile-time).
-template <int I>
+// velocity I (compile-time).  ORDER 2 drops the third-order Hermite terms of
+// both parts (the regularised collision of Eq. (fullstrcoll)).
+template <int I, int ORDER = 3>
 __device__ __forceinline__ float emit_dev(const NodeTerms& t, float one_minus_omega) {
     constexpr int X = cx_of(I), Y = cy_of(I), Z = cz_of(I);
     constexpr float W = w216_of(I);
@@ -167,8 +168,12 @@ __device__ __forceinline__ float emit_dev(const NodeTerms& t, float one_minus_om
                       2.0f * (X * Y * t.p[3] + X * Z * t.p[4] + Y * Z * t.p[5]);
     const float cpu = X * t.pu[0] + Y * t.pu[1] + Z * t.pu[2];
     const float cg = X * t.rg[0] + Y * t.rg[1] + Z * t.rg[2];
-    const float eq = cu * (3.0f + 4.5f * cu) - 1.5f * t.u2 + 4.5f * cu * (cu * cu - t.u2);
-    const float neq = 4.5f * cpc - 1.5f * t.trp + cu * (13.5f * cpc - 4.5f * t.trp) - 9.0f * cpu;
+    float eq = cu * (3.0f + 4.5f * cu) - 1.5f * t.u2;
+    float neq = 4.5f * cpc - 1.5f * t.trp;
+    if constexpr (ORDER >= 3) {
+        eq += 4.5f * cu * (cu * cu - t.u2);
+        neq += cu * (13.5f * cpc - 4.5f * t.trp) - 9.0f * cpu;
+    }
     return W * (t.drho + t.rho * eq + one_minus_omega * neq + 3.0f * cg);
 }
 

@@ -13,6 +13,8 @@ namespace tslb {
 struct StepParams {
     Geometry geo;
     float one_minus_omega;   // 1 - 1/tau
+    int order;               // Hermite order of the rebuilt populations (2 or 3)
+    const float* omo_z;      // optional 1 - omega per z plane (nz floats), else one_minus_omega
     float force[3];          // uniform acceleration (used when gfield == nullptr)
     const float* gfield;     // optional per-node acceleration, 3N SoA
     float scale[3];          // storage scales (drho, u, Pi); 1 for FP32
@@ -34,11 +36,19 @@ struct InletParams {
     float radius2;
     float amp;               // noise * |u|
     uint64_t seed;
+    int noise_kind;          // 0 uniform in [-1, 1), 1 standard Gaussian
 };
+
+// 1 - omega of the nodes of plane z.
+__device__ __forceinline__ float omo_at(const StepParams& p, int z) {
+    return p.omo_z ? p.omo_z[z] : p.one_minus_omega;
+}
 
 // Launchers (stream-ordered, no synchronisation).  `storage` selects the
 // stored format (0 FP32, 1 FP16, 2 BF16); buffers are the raw state arrays.
 hipError_t launch_update_direct(int storage, const void* in, void* out, const StepParams& p, hipStream_t s);
+hipError_t launch_update_poplayout(int storage, const void* in, void* out, float* pop, const StepParams& p,
+                                   hipStream_t s);
 hipError_t launch_update_tiled(int storage, const void* in, void* out, const StepParams& p, hipStream_t s);
 // Completes the wall-adjacent nodes after launch_update_tiled (walls only).
 hipError_t launch_wall_fixup(int storage, const void* in, void* out, const StepParams& p, hipStream_t s);
@@ -54,6 +64,8 @@ hipError_t launch_reduce(int storage, const void* st, double* partials, int nblo
 hipError_t launch_adjoint_seed(const float* st, float* lam, const StepParams& p, hipStream_t s);
 hipError_t launch_adjoint_step(const float* st0, const float* st1, const float* lam1, float* lam0, float* dg,
                                const StepParams& p, hipStream_t s);
+hipError_t launch_adjoint_tiled(const float* st0, const float* st1, const float* lam1, float* lam0, float* dg,
+                                const StepParams& p, hipStream_t s);
 
 }  // namespace tslb
 
@@ -71,6 +83,8 @@ struct tslb_ctx {
     double* red_out;         // 6 doubles
     int red_blocks;
     int64_t t;               // current level
-    int kernel;              // 0 tiled, 1 direct
+    int kernel;              // 0 tiled, 1 direct, 2 population layout
+    float* pop;              // 27 N populations of the population-layout variant (lazily)
+    float* omo_z;            // owned per-plane 1 - omega (or null)
     bool has_ghosts;
 };

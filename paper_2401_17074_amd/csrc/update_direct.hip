@@ -17,7 +17,7 @@ __device__ __forceinline__ void load_moments(const typename S::T* st, long long 
     for (int q = 4; q < 10; ++q) m[q] = S::load(st[q * N + n], inv[2]);
 }
 
-template <class S>
+template <class S, int ORDER>
 __global__ void __launch_bounds__(256) update_direct_kernel(const typename S::T* __restrict__ in,
                                                             typename S::T* __restrict__ out, StepParams p) {
     const Geometry& g = p.geo;
@@ -44,14 +44,14 @@ __global__ void __launch_bounds__(256) update_direct_kernel(const typename S::T*
             load_moments<S>(in, g.N, n, p.inv_scale, m);
 #pragma unroll
             for (int a = 0; a < 3; ++a) gg[a] = p.gfield ? p.gfield[a * g.N + n] : p.force[a];
-            f = emit_dev<26 - I>(node_terms(m, gg), p.one_minus_omega);
+            f = emit_dev<26 - I, ORDER>(node_terms(m, gg), omo_at(p, z));
         } else {
             const long long src = sx + (long long)g.n[0] * (sy + (long long)g.n[1] * sz);
             float m[10], gg[3];
             load_moments<S>(in, g.N, src, p.inv_scale, m);
 #pragma unroll
             for (int a = 0; a < 3; ++a) gg[a] = p.gfield ? p.gfield[a * g.N + src] : p.force[a];
-            f = emit_dev<I>(node_terms(m, gg), p.one_minus_omega);
+            f = emit_dev<I, ORDER>(node_terms(m, gg), omo_at(p, sz));
         }
         acc.template add<I>(f);
     });
@@ -68,8 +68,12 @@ template <class S>
 hipError_t launch(const void* in, void* out, const StepParams& p, hipStream_t s) {
     const int block = 256;
     const long long grid = (p.geo.N + block - 1) / block;
-    hipLaunchKernelGGL(update_direct_kernel<S>, dim3((unsigned)grid), dim3(block), 0, s,
-                       (const typename S::T*)in, (typename S::T*)out, p);
+    if (p.order == 2)
+        hipLaunchKernelGGL((update_direct_kernel<S, 2>), dim3((unsigned)grid), dim3(block), 0, s,
+                           (const typename S::T*)in, (typename S::T*)out, p);
+    else
+        hipLaunchKernelGGL((update_direct_kernel<S, 3>), dim3((unsigned)grid), dim3(block), 0, s,
+                           (const typename S::T*)in, (typename S::T*)out, p);
     return hipGetLastError();
 }
 

@@ -23,252 +23,18 @@
 // populations with (cx, cy) != (0, 0) go through LDS; the three with
 // cx = cy = 0 stay in the thread.  Contributions to the output planes
 // p - 1, p, p + 1 are accumulated in three rolling register sets.
-#include "tslb_internal.h"
+#include "tslb_tiles.h"
 
 namespace tslb {
 namespace {
 
-#ifndef TSLB_TILE_X
-#define TSLB_TILE_X 64
-#endif
-#ifndef TSLB_TILE_Y
-#define TSLB_TILE_Y 12
-#endif
-#ifndef TSLB_NT_STORE
-#define TSLB_NT_STORE 1
-#endif
-#ifndef TSLB_WAVES_PER_EU
-#define TSLB_WAVES_PER_EU 4
-#endif
-constexpr int TX = TSLB_TILE_X;              // interior tile width (64: one wave per row)
-constexpr int TY = TSLB_TILE_Y;              // interior rows
-constexpr int LX = TX + 2, LY = TY + 2;      // LDS tile with halo
-constexpr int NINT = TX * TY;                // interior threads (whole waves)
-constexpr int NHALO = 2 * LX + 2 * TY;       // halo columns
-constexpr int NTHREADS = NINT + ((NHALO + 63) / 64) * 64;
-constexpr int NSLOT = 24;                    // populations with (cx, cy) != (0, 0)
+using namespace tile;
 
-__host__ __device__ constexpr int slot_of(int I) { return I - (I > 4) - (I > 13) - (I > 22); }
 
-// monomial coefficient indices: K<ex><ey><ez> multiplies cx^ex cy^ey cz^ez
-enum {
-    K000, K100, K010, K001, K200, K020, K002, K110, K101, K011,
-    K210, K201, K120, K021, K102, K012, K111, NK
-};
-
-// Coefficients of P(c) = sum_k A_k m_k(c) for a node with moments m
-// (drho, u, Pi) and acceleration g; omo = 1 - omega (see tslb_device.h for
-// P).  Equilibrium part from expanding rho [3 cu + 9/2 cu^2 - 3/2 u^2 +
-// 9/2 cu^3 - 9/2 cu u^2] with c_a^3 = c_a; non-equilibrium part from
-// (1 - omega) [9/2 cPc - 3/2 tr Pi + 27/2 cPc cu - 9/2 tr Pi cu - 9 c.Pi u].
-__device__ __forceinline__ void coefficients(const float m[10], const float g[3], float omo, float A[NK]) {
-    const float dr = m[0], rho = 1.0f + dr;
-    const float ux = m[1], uy = m[2], uz = m[3];
-    const float pxx = omo * m[4], pyy = omo * m[5], pzz = omo * m[6];
-    const float pxy = omo * m[7], pxz = omo * m[8], pyz = omo * m[9];
-    const float rx = rho * ux, ry = rho * uy, rz = rho * uz;
-    const float uxx = ux * ux, uyy = uy * uy, uzz = uz * uz;
-    const float u2 = uxx + uyy + uzz;
-    const float tr = pxx + pyy + pzz;
-    A[K000] = dr - 1.5f * (rho * u2 + tr);
-    A[K200] = 4.5f * (rx * ux + pxx);
-    A[K020] = 4.5f * (ry * uy + pyy);
-    A[K002] = 4.5f * (rz * uz + pzz);
-    A[K110] = 9.0f * (rx * uy + pxy);
-    A[K101] = 9.0f * (rx * uz + pxz);
-    A[K011] = 9.0f * (ry * uz + pyz);
-    const float base = 3.0f - 4.5f * u2;
-    const float pux = pxx * ux + pxy * uy + pxz * uz;
-    const float puy = pxy * ux + pyy * uy + pyz * uz;
-    const float puz = pxz * ux + pyz * uy + pzz * uz;
-    const float t45 = 4.5f * tr;
-    A[K100] = rx * (base + 4.5f * uxx) + ux * (13.5f * pxx - t45) - 9.0f * pux + 3.0f * rho * g[0];
-    A[K010] = ry * (base + 4.5f * uyy) + uy * (13.5f * pyy - t45) - 9.0f * puy + 3.0f * rho * g[1];
-    A[K001] = rz * (base + 4.5f * uzz) + uz * (13.5f * pzz - t45) - 9.0f * puz + 3.0f * rho * g[2];
-    A[K210] = 13.5f * (rx * ux * uy + pxx * uy + 2.0f * pxy * ux);
-    A[K201] = 13.5f * (rx * ux * uz + pxx * uz + 2.0f * pxz * ux);
-    A[K120] = 13.5f * (ry * uy * ux + pyy * ux + 2.0f * pxy * uy);
-    A[K021] = 13.5f * (ry * uy * uz + pyy * uz + 2.0f * pyz * uy);
-    A[K102] = 13.5f * (rz * uz * ux + pzz * ux + 2.0f * pxz * uz);
-    A[K012] = 13.5f * (rz * uz * uy + pzz * uy + 2.0f * pyz * uz);
-    A[K111] = 27.0f * (rx * uy * uz + pxy * uz + pxz * uy + pyz * ux);
-}
-
-// Values of the 2D polynomial Q(cx, cy) = sum b_ab cx^a cy^b on the 3 x 3
-// velocity grid of one cz slice, written to G[base + 3 (cy + 1) + (cx + 1)]
-// with the exact weight factor 4^n0 applied.
-template <int CZ>
-__device__ __forceinline__ void eval_slice(float b00, float b10, float b01, float b20, float b02, float b11, float b21,
-                                           float b12, float G[27]) {
-    // along x for each power of cy
-    const float s0 = b00 + b20, s1 = b01 + b21;
-    const float r0[3] = {s0 - b10, b00, s0 + b10};
-    const float r1[3] = {s1 - b11, b01, s1 + b11};
-    const float r2[3] = {b02 - b12, b02, b02 + b12};
-#pragma unroll
-    for (int ix = 0; ix < 3; ++ix) {
-        const float t = r0[ix] + r2[ix];
-        const float q[3] = {t - r1[ix], r0[ix], t + r1[ix]};
-#pragma unroll
-        for (int iy = 0; iy < 3; ++iy) {
-            const int I = 9 * (CZ + 1) + 3 * iy + ix;
-            const float w = (float)(1 << (2 * ((ix == 1) + (iy == 1) + (CZ == 0))));
-            G[I] = (w == 1.0f) ? q[iy] : w * q[iy];
-        }
-    }
-}
-
-__device__ __forceinline__ void populations(const float A[NK], float G[27]) {
-    eval_slice<0>(A[K000], A[K100], A[K010], A[K200], A[K020], A[K110], A[K210], A[K120], G);
-    const float e00 = A[K000] + A[K002], e10 = A[K100] + A[K102], e01 = A[K010] + A[K012];
-    eval_slice<1>(e00 + A[K001], e10 + A[K101], e01 + A[K011], A[K200] + A[K201], A[K020] + A[K021],
-                  A[K110] + A[K111], A[K210], A[K120], G);
-    eval_slice<-1>(e00 - A[K001], e10 - A[K101], e01 - A[K011], A[K200] - A[K201], A[K020] - A[K021],
-                   A[K110] - A[K111], A[K210], A[K120], G);
-}
-
-// Moments of one arriving cz slice F[cy+1][cx+1], added to the output plane
-// accumulator: sum F, sum F c and sum F c c with c = (cx, cy, CZ).
-template <int CZ, bool ASSIGN = false>
-__device__ __forceinline__ void add_slice(const float F[3][3], MomentSums& a) {
-    float s[3], d[3], t[3];
-#pragma unroll
-    for (int r = 0; r < 3; ++r) {
-        s[r] = F[r][0] + F[r][2];
-        d[r] = F[r][2] - F[r][0];
-        t[r] = s[r] + F[r][1];
-    }
-    const float m02 = t[2] + t[0];
-    const float m00 = m02 + t[1];
-    const float m01 = t[2] - t[0];
-    const float m10 = d[0] + d[1] + d[2];
-    const float m11 = d[2] - d[0];
-    const float m20 = s[0] + s[1] + s[2];
-    if constexpr (ASSIGN) {
-        // first contribution to a fresh output plane (only the CZ != 0 slices
-        // touch all ten sums)
-        static_assert(CZ != 0, "assignment needs a slice that covers every moment");
-        a.d = m00;
-        a.j[0] = m10;
-        a.j[1] = m01;
-        a.s[0] = m20;
-        a.s[1] = m02;
-        a.s[3] = m11;
-        a.j[2] = CZ * m00;
-        a.s[2] = m00;
-        a.s[4] = CZ * m10;
-        a.s[5] = CZ * m01;
-    } else {
-        a.d += m00;
-        a.j[0] += m10;
-        a.j[1] += m01;
-        a.s[0] += m20;
-        a.s[1] += m02;
-        a.s[3] += m11;
-        if (CZ != 0) {
-            a.j[2] += CZ * m00;
-            a.s[2] += m00;
-            a.s[4] += CZ * m10;
-            a.s[5] += CZ * m01;
-        }
-    }
-}
-
-// Output stores: the new level is not read again by this launch, so it may
-// bypass L2 allocation (non-temporal) and leave the cache to the halo reads.
-template <class T>
-__device__ __forceinline__ void store_out(T* p, T v) {
-    if constexpr (TSLB_NT_STORE) {
-        if constexpr (sizeof(T) == 4)
-            __builtin_nontemporal_store(__builtin_bit_cast(float, v), reinterpret_cast<float*>(p));
-        else
-            __builtin_nontemporal_store(__builtin_bit_cast(unsigned short, v), reinterpret_cast<unsigned short*>(p));
-    } else {
-        *p = v;
-    }
-}
-
-// Field q of node n: a uniform per-field base plus a 32-bit node offset, so
-// the address is one scalar base and one shared vector offset (the grid
-// holds fewer than 2^30 nodes, checked at launch).
-template <class T>
-__device__ __forceinline__ T ld_at(const T* __restrict__ base, unsigned byte_off) {
-    return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + byte_off);
-}
-
-template <class T>
-__device__ __forceinline__ T* at(T* base, unsigned byte_off) {
-    return reinterpret_cast<T*>(reinterpret_cast<char*>(base) + byte_off);
-}
-
-// Per-field base pointers, passed as kernel arguments so each one sits in
-// scalar registers and every access is that base plus one shared 32-bit
-// vector offset (no per-field 64-bit address arithmetic).
-template <class T>
-struct FieldPtrs {
-    const T* in[10];
-    T* out[10];
-    const float* g[3];
-};
-
-template <class S>
-__device__ __forceinline__ void load_node(const FieldPtrs<typename S::T>& f, unsigned n, const StepParams& p,
-                                          float m[10]) {
-    const unsigned off = n * (unsigned)sizeof(typename S::T);
-    m[0] = S::load(ld_at(f.in[0], off), p.inv_scale[0]);
-#pragma unroll
-    for (int q = 1; q < 4; ++q) m[q] = S::load(ld_at(f.in[q], off), p.inv_scale[1]);
-#pragma unroll
-    for (int q = 4; q < 10; ++q) m[q] = S::load(ld_at(f.in[q], off), p.inv_scale[2]);
-}
-
-// Plane index of zp in [-1, nz]: one wrap for a periodic axis, else clamp.
-__device__ __forceinline__ int plane_index(int zp, int nz, bool periodic) {
-    if (periodic) return zp < 0 ? zp + nz : (zp >= nz ? zp - nz : zp);
-    return zp < 0 ? 0 : (zp >= nz ? nz - 1 : zp);
-}
-
-// In-range index of coordinate v on an axis of n nodes: periodic axes wrap
-// (any v, so lanes of a tile wider than the grid stay in bounds), others clamp
-// (clamped values are never used by a fluid node).
-__device__ __forceinline__ int wrap_or_clamp(int v, int n, bool periodic) {
-    if (periodic) {
-        v %= n;
-        return v < 0 ? v + n : v;
-    }
-    return v < 0 ? 0 : (v >= n ? n - 1 : v);
-}
-
-// Per-lane wall flags of an interior column: bit 0 lo-x, 1 hi-x, 2 lo-y,
-// 3 hi-y set when the neighbour on that side is a wall node.
-__device__ __forceinline__ int wall_flags(const Geometry& g, int gx, int gy) {
-    int f = 0;
-    f |= ((g.lo_solid & 1) && gx == 1) ? 1 : 0;
-    f |= ((g.hi_solid & 1) && gx == g.n[0] - 2) ? 2 : 0;
-    f |= ((g.lo_solid & 2) && gy == 1) ? 4 : 0;
-    f |= ((g.hi_solid & 2) && gy == g.n[1] - 2) ? 8 : 0;
-    return f;
-}
-
-// Is the upstream node of direction I solid, for an output node with
-// in-plane flags wf and z flags zlo (plane below is a wall) / zhi?
-template <int I>
-__device__ __forceinline__ bool upstream_solid(int wf, bool zlo, bool zhi) {
-    constexpr int X = cx_of(I), Y = cy_of(I), Z = cz_of(I);
-    bool s = false;
-    if (X == 1) s |= (wf & 1) != 0;
-    if (X == -1) s |= (wf & 2) != 0;
-    if (Y == 1) s |= (wf & 4) != 0;
-    if (Y == -1) s |= (wf & 8) != 0;
-    if (Z == 1) s |= zlo;
-    if (Z == -1) s |= zhi;
-    return s;
-}
-
-template <class S, bool WALLS, bool FIELD>
+template <class S, bool WALLS, bool FIELD, int ORDER>
 __global__ void __launch_bounds__(NTHREADS, TSLB_WAVES_PER_EU) update_tiled_kernel(const FieldPtrs<typename S::T> f, StepParams p,
                                                                    int tiles_x, int tiles_y, int tiles_z, int TZ) {
-    __shared__ float lds[NSLOT][LY][LX];
+    __shared__ float lds_all[NBUF][NSLOT][LY][LX];
     const Geometry& g = p.geo;
     const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
     const unsigned plane_nodes = (unsigned)nx * (unsigned)ny;
@@ -354,8 +120,11 @@ __global__ void __launch_bounds__(NTHREADS, TSLB_WAVES_PER_EU) update_tiled_kern
     // starts here), then store the completed plane zp - 1.
     auto plane = [&](int zp, MomentSums& aprev, MomentSums& acur, MomentSums& anext) {
         const unsigned node = col + plane_nodes * (unsigned)plane_index(zp, nz, pz);
+        float(&lds)[NSLOT][LY][LX] = lds_all[NBUF == 2 ? ((zp - zs + 1) & 1) : 0];
         float mnext[10];
         const bool have_next = zp + 1 <= ze;
+        if (TSLB_EARLY_PREFETCH && active && have_next)
+            load_node<S>(f, col + plane_nodes * (unsigned)plane_index(zp + 1, nz, pz), p, mnext);
 
         float G[27];
         if (active) {
@@ -364,14 +133,15 @@ __global__ void __launch_bounds__(NTHREADS, TSLB_WAVES_PER_EU) update_tiled_kern
                 for (int a = 0; a < 3; ++a) gacc[a] = gon * ld_at(f.g[a], node * 4u);
             }
             float A[NK];
+            const float omo = omo_at(p, plane_index(zp, nz, pz));
             if (WALLS) {
                 // a wall plane (z walls) emits nothing either
                 const bool plane_solid = (zlo_wall && zp == 0) || (zhi_wall && zp == nz - 1);
                 const float gp = plane_solid ? 0.0f : 1.0f;
                 const float gz[3] = {gp * gacc[0], gp * gacc[1], gp * gacc[2]};
-                coefficients(mcur, gz, p.one_minus_omega, A);
+                coefficients<ORDER>(mcur, gz, omo, A);
             } else {
-                coefficients(mcur, gacc, p.one_minus_omega, A);
+                coefficients<ORDER>(mcur, gacc, omo, A);
             }
             populations(A, G);
             Unroll<0, 27>::run([&]<int I>() {
@@ -379,7 +149,8 @@ __global__ void __launch_bounds__(NTHREADS, TSLB_WAVES_PER_EU) update_tiled_kern
             });
             // prefetch the next plane once this plane's moments are consumed;
             // the loads are in flight across the exchange and the gather
-            if (have_next) load_node<S>(f, col + plane_nodes * (unsigned)plane_index(zp + 1, nz, pz), p, mnext);
+            if (!TSLB_EARLY_PREFETCH && have_next)
+                load_node<S>(f, col + plane_nodes * (unsigned)plane_index(zp + 1, nz, pz), p, mnext);
         }
         __syncthreads();
         if (interior) {
@@ -433,7 +204,7 @@ __global__ void __launch_bounds__(NTHREADS, TSLB_WAVES_PER_EU) update_tiled_kern
 #pragma unroll
             for (int q = 0; q < 10; ++q) mcur[q] = mnext[q];
         }
-        __syncthreads();
+        if (NBUF == 1) __syncthreads();
     };
 
     // Rolling roles of the three accumulators, unrolled to their period so
@@ -456,7 +227,7 @@ __global__ void __launch_bounds__(NTHREADS, TSLB_WAVES_PER_EU) update_tiled_kern
 // the raw sums the update left in the side buffer, then finalises and
 // stores.  Threads enumerate the layers next to each wall face; a node next
 // to several walls is done once, by its first wall face.
-template <class S>
+template <class S, int ORDER>
 __global__ void __launch_bounds__(256) wall_fixup_kernel(const FieldPtrs<typename S::T> f, StepParams p,
                                                          long long total) {
     const Geometry& g = p.geo;
@@ -486,7 +257,7 @@ __global__ void __launch_bounds__(256) wall_fixup_kernel(const FieldPtrs<typenam
 #pragma unroll
     for (int a = 0; a < 3; ++a) gg[a] = f.g[a] ? ld_at(f.g[a], node * 4u) : p.force[a];
     float A[NK], G[27];
-    coefficients(m, gg, p.one_minus_omega, A);
+    coefficients<ORDER>(m, gg, omo_at(p, c[2]), A);
     populations(A, G);
 
     const float* side = p.wall_side + 10 * local + 10 * p.wall_off[fw];
@@ -511,49 +282,7 @@ __global__ void __launch_bounds__(256) wall_fixup_kernel(const FieldPtrs<typenam
     for (int q = 4; q < 10; ++q) *at(f.out[q], on) = S::store(out[q], p.scale[2]);
 }
 
-template <class S>
-FieldPtrs<typename S::T> field_ptrs(const void* in, void* out, const StepParams& p) {
-    using T = typename S::T;
-    FieldPtrs<T> f;
-    for (int q = 0; q < 10; ++q) {
-        f.in[q] = (const T*)in + (size_t)q * p.geo.N;
-        f.out[q] = (T*)out + (size_t)q * p.geo.N;
-    }
-    for (int a = 0; a < 3; ++a) f.g[a] = p.gfield ? p.gfield + (size_t)a * p.geo.N : nullptr;
-    return f;
-}
-
-// Planes per block: every block costs about (tz + 2) plane-steps and the
-// blocks run in rounds of one per CU, so pick the tz in [16, 64] that
-// minimises rounds * (tz + 2) (fewer halo planes vs. a ragged last round).
-inline int choose_tz(int columns, int nz, int cus) {
-    int best = 32;
-    long long best_cost = -1;
-    for (int tz = 16; tz <= 64; ++tz) {
-        const long long blocks = (long long)columns * ((nz + tz - 1) / tz);
-        const long long rounds = (blocks + cus - 1) / cus;
-        const long long cost = rounds * (tz + 2);
-        if (best_cost < 0 || cost < best_cost) {
-            best_cost = cost;
-            best = tz;
-        }
-    }
-    return best;
-}
-
-inline int compute_units() {
-    static int cus = 0;
-    if (cus == 0) {
-        int dev = 0;
-        hipDeviceProp_t prop;
-        if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
-            cus = prop.multiProcessorCount;
-        if (cus <= 0) cus = 256;
-    }
-    return cus;
-}
-
-template <class S, bool WALLS, bool FIELD>
+template <class S, bool WALLS, bool FIELD, int ORDER>
 hipError_t launch_t(const void* in, void* out, const StepParams& p, hipStream_t s) {
     const int tiles_x = (p.geo.n[0] + TX - 1) / TX;
     const int tiles_y = (p.geo.n[1] + TY - 1) / TY;
@@ -562,17 +291,23 @@ hipError_t launch_t(const void* in, void* out, const StepParams& p, hipStream_t 
     const unsigned nblk = (unsigned)tiles_x * tiles_y * tiles_z;
     if (p.geo.N >= (1LL << 30)) return hipErrorInvalidValue;  // 32-bit node offsets
     const FieldPtrs<typename S::T> f = field_ptrs<S>(in, out, p);
-    hipLaunchKernelGGL((update_tiled_kernel<S, WALLS, FIELD>), dim3(nblk), dim3(NTHREADS), 0, s, f, p, tiles_x,
+    hipLaunchKernelGGL((update_tiled_kernel<S, WALLS, FIELD, ORDER>), dim3(nblk), dim3(NTHREADS), 0, s, f, p, tiles_x,
                        tiles_y, tiles_z, TZ);
     return hipGetLastError();
 }
 
-template <class S>
-hipError_t launch_s(const void* in, void* out, const StepParams& p, hipStream_t s) {
+template <class S, int ORDER>
+hipError_t launch_o(const void* in, void* out, const StepParams& p, hipStream_t s) {
     const bool walls = (p.geo.lo_solid | p.geo.hi_solid) != 0;
     const bool field = p.gfield != nullptr;
-    if (walls) return field ? launch_t<S, true, true>(in, out, p, s) : launch_t<S, true, false>(in, out, p, s);
-    return field ? launch_t<S, false, true>(in, out, p, s) : launch_t<S, false, false>(in, out, p, s);
+    if (walls)
+        return field ? launch_t<S, true, true, ORDER>(in, out, p, s) : launch_t<S, true, false, ORDER>(in, out, p, s);
+    return field ? launch_t<S, false, true, ORDER>(in, out, p, s) : launch_t<S, false, false, ORDER>(in, out, p, s);
+}
+
+template <class S>
+hipError_t launch_s(const void* in, void* out, const StepParams& p, hipStream_t s) {
+    return p.order == 2 ? launch_o<S, 2>(in, out, p, s) : launch_o<S, 3>(in, out, p, s);
 }
 
 }  // namespace
@@ -583,7 +318,10 @@ hipError_t fixup_s(const void* in, void* out, const StepParams& p, hipStream_t s
     const FieldPtrs<typename S::T> f = field_ptrs<S>(in, out, p);
     const int block = 256;
     const unsigned grid = (unsigned)((p.wall_nodes + block - 1) / block);
-    hipLaunchKernelGGL(wall_fixup_kernel<S>, dim3(grid), dim3(block), 0, s, f, p, p.wall_nodes);
+    if (p.order == 2)
+        hipLaunchKernelGGL((wall_fixup_kernel<S, 2>), dim3(grid), dim3(block), 0, s, f, p, p.wall_nodes);
+    else
+        hipLaunchKernelGGL((wall_fixup_kernel<S, 3>), dim3(grid), dim3(block), 0, s, f, p, p.wall_nodes);
     return hipGetLastError();
 }
 

@@ -17,12 +17,13 @@ class Solver:
 
     def __init__(self, nx, ny, nz, tau, force=(0.0, 0.0, 0.0), faces=(C.TSLB_PERIODIC,) * 6,
                  storage=C.TSLB_FP32, scale=(0.0, 0.0, 0.0), inlet_u=(0.0, 0.0, 0.0), inlet_center=(0.0, 0.0),
-                 inlet_radius=0.0, inlet_noise=0.0, seed=0, kernel=None):
+                 inlet_radius=0.0, inlet_noise=0.0, seed=0, kernel=None, order=3, inlet_noise_kind=0):
         self.shape = (nz, ny, nx)
         self.N = nx * ny * nz
         self.device = torch.device("cuda", torch.cuda.current_device())
         bc = C.make_bc(faces=faces, inlet_u=inlet_u, inlet_center=inlet_center, inlet_radius=inlet_radius,
-                       inlet_noise=inlet_noise, seed=seed, storage=storage, scale=scale)
+                       inlet_noise=inlet_noise, seed=seed, storage=storage, scale=scale, order=order,
+                       inlet_noise_kind=inlet_noise_kind)
         self.h = C.tslb_create(nx, ny, nz, C.TSLB_D3Q27, tau, force, bc)
         if kernel is not None:
             C.tslb_set_kernel(self.h, kernel)
@@ -61,6 +62,17 @@ class Solver:
 
     def step(self, n=1):
         C.tslb_step(self.h, n)
+
+    def set_relaxation_profile(self, tau_z):
+        """Relaxation time per z plane (nz values), or None for the uniform tau."""
+        if tau_z is not None:
+            assert len(tau_z) == self.shape[0]
+        C.tslb_set_relaxation_profile(self.h, tau_z)
+
+    def step_timed(self, n):
+        """n steps; returns (ms in the main update kernel, ms in the per-step
+        auxiliary launches), summed over the steps."""
+        return C.tslb_step_timed(self.h, n)
 
     @property
     def t(self):

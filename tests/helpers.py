@@ -15,11 +15,18 @@ def f32(x):
     return float(F32(x))
 
 
+def _tau_z32(case):
+    import workloads as W
+    prof = W.tau_profile(case)
+    return None if prof is None else [f32(v) for v in prof]
+
+
 def oracle_grid(case):
     return oracle.make_grid(case.nx, case.ny, case.nz, f32(case.tau), faces=case.faces,
                             force=[f32(v) for v in case.force], inlet_u=[f32(v) for v in case.inlet_u],
                             inlet_center=[f32(v) for v in case.inlet_center], inlet_radius=f32(case.inlet_radius),
-                            inlet_noise=_amp_ratio(case), seed=case.seed)
+                            inlet_noise=_amp_ratio(case), seed=case.seed, order=case.order,
+                            noise_kind=case.noise_kind, tau_z=_tau_z32(case))
 
 
 def _amp_ratio(case):
@@ -36,9 +43,14 @@ def _amp_ratio(case):
 
 def gpu_solver(case, storage=0, kernel=None, scale=(0.0, 0.0, 0.0)):
     from paper_2401_17074_amd import Solver
-    return Solver(case.nx, case.ny, case.nz, f32(case.tau), force=[f32(v) for v in case.force], faces=case.faces,
-                  storage=storage, scale=scale, inlet_u=case.inlet_u, inlet_center=case.inlet_center,
-                  inlet_radius=case.inlet_radius, inlet_noise=case.inlet_noise, seed=case.seed, kernel=kernel)
+    s = Solver(case.nx, case.ny, case.nz, f32(case.tau), force=[f32(v) for v in case.force], faces=case.faces,
+               storage=storage, scale=scale, inlet_u=case.inlet_u, inlet_center=case.inlet_center,
+               inlet_radius=case.inlet_radius, inlet_noise=case.inlet_noise, seed=case.seed, kernel=kernel,
+               order=case.order, inlet_noise_kind=case.noise_kind)
+    tz = _tau_z32(case)
+    if tz is not None:
+        s.set_relaxation_profile(tz)
+    return s
 
 
 def to_device_state(st64):

@@ -28,7 +28,7 @@ def lib():
 
 def test_every_declared_symbol_is_exported(lib):
     names = _declared()
-    assert len(names) == 19
+    assert len(names) == 21
     for n in names:
         assert hasattr(lib, n), n
 
@@ -41,7 +41,7 @@ def test_binding_covers_the_header():
 def test_struct_layout_matches_header():
     from paper_2401_17074_amd import _binding
     # int[6], float[3], float[2], float, float, (pad to 8) uint64, int, float[3]
-    assert ctypes.sizeof(_binding.tslb_bc) == 80
+    assert ctypes.sizeof(_binding.tslb_bc) == 88
     assert _binding.tslb_bc.seed.offset == 56
 
 

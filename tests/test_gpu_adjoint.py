@@ -23,17 +23,18 @@ def _rel(a, b):
     return float(np.abs(a - b).max() / np.abs(b).max())
 
 
-@pytest.mark.parametrize("faces", [(0,) * 6, (0, 0, 1, 1, 0, 0)])
-def test_one_adjoint_step_matches_oracle(faces):
+@pytest.mark.parametrize("kernel", [0, 1])
+@pytest.mark.parametrize("faces", [(0,) * 6, (0, 0, 1, 1, 0, 0), (1, 1, 0, 0, 1, 1)])
+def test_one_adjoint_step_matches_oracle(faces, kernel):
     import torch
-    case = W.Case("adj1", 19, 14, 11, 0.62, faces=faces)
+    case = W.Case("adj1", 71, 26, 19, 0.62, faces=faces)
     st0 = W.to_fp32(W.random_state(case.shape, seed=201, u_amp=0.05, pi_amp=2e-3))
     g = W.random_force(case.shape, seed=202, amp=1e-4).astype(np.float32).astype(np.float64)
     lam1 = np.random.default_rng(203).standard_normal(st0.shape).astype(np.float32).astype(np.float64)
     G = oracle_grid(case)
     kinds = oracle.node_kinds(G)
     lam1[:, kinds != 0] = 0.0
-    s = gpu_solver(case)
+    s = gpu_solver(case, kernel=kernel)
     s.set_force_field(g)
     s.set_state(to_device_state(st0))
     raw0 = s.save_raw()
@@ -49,7 +50,8 @@ def test_one_adjoint_step_matches_oracle(faces):
     assert _rel(dg, want_dg) < 1e-5
 
 
-def test_checkpointed_rollout_gradient_matches_oracle():
+@pytest.mark.parametrize("kernel", [0, 1])
+def test_checkpointed_rollout_gradient_matches_oracle(kernel):
     """TslbRollout (checkpoint every 7 of 30 steps) on a 16^3 forced periodic
     box: dL/dg and dL/du0 against the oracle's stored-trajectory adjoint."""
     import torch
@@ -60,7 +62,7 @@ def test_checkpointed_rollout_gradient_matches_oracle():
     g = g.astype(np.float32).astype(np.float64)
     G = oracle_grid(case)
     L_or, lam0_or, dg_or = oracle.rollout_grad(G, st0, case.steps, g)
-    s = gpu_solver(case)
+    s = gpu_solver(case, kernel=kernel)
     gt = torch.tensor(g, dtype=torch.float32, device="cuda", requires_grad=True)
     ut = torch.tensor(st0[1:4], dtype=torch.float32, device="cuda", requires_grad=True)
     L = TslbRollout.apply(gt, ut, s, case.steps, case.extra["ckpt"])
@@ -71,7 +73,8 @@ def test_checkpointed_rollout_gradient_matches_oracle():
     assert _rel(ut.grad.double().cpu().numpy(), lam0_or[1:4]) < 1e-4
 
 
-def test_full_size_adjoint_step_sampled():
+@pytest.mark.parametrize("kernel", [0, 1])
+def test_full_size_adjoint_step_sampled(kernel):
     """64^3 forced periodic box of the differentiable workload: one adjoint
     step at the step the rollout uses, checked at sampled nodes."""
     import torch
@@ -80,7 +83,7 @@ def test_full_size_adjoint_step_sampled():
     st0 = W.to_fp32(st0)
     g = g.astype(np.float32).astype(np.float64)
     G = oracle_grid(case)
-    s = gpu_solver(case)
+    s = gpu_solver(case, kernel=kernel)
     s.set_force_field(g)
     s.set_state(to_device_state(st0))
     s.step(3)
@@ -97,3 +100,33 @@ def test_full_size_adjoint_step_sampled():
     want, _ = oracle.adjoint_nodes(G, pre, lam1, idx, g)
     got = lam0.reshape(10, -1)[:, idx]
     assert _rel(got, want) < 1e-5
+
+
+@pytest.mark.parametrize("kernel", [0, 1])
+@pytest.mark.parametrize("faces", [(0,) * 6, (0, 0, 1, 1, 0, 0)])
+def test_adjoint_step_with_relaxation_profile(faces, kernel):
+    """One adjoint step when tau changes from plane to plane: each emitted
+    population is differentiated with the tau of its emitter's plane."""
+    import torch
+    case = W.Case("adj_sponge", 69, 21, 17, 0.62, faces=faces)
+    tau_z = [float(np.float32(v)) for v in np.random.default_rng(210).uniform(0.55, 1.5, case.nz)]
+    st0 = W.to_fp32(W.random_state(case.shape, seed=211, u_amp=0.05, pi_amp=2e-3))
+    g = W.random_force(case.shape, seed=212, amp=1e-4).astype(np.float32).astype(np.float64)
+    lam1 = np.random.default_rng(213).standard_normal(st0.shape).astype(np.float32).astype(np.float64)
+    G = oracle.make_grid(case.nx, case.ny, case.nz, float(np.float32(case.tau)), faces=faces, tau_z=tau_z)
+    lam1[:, oracle.node_kinds(G) != 0] = 0.0
+    s = gpu_solver(case, kernel=kernel)
+    s.set_relaxation_profile(tau_z)
+    s.set_force_field(g)
+    s.set_state(to_device_state(st0))
+    raw0 = s.save_raw()
+    s.step(1)
+    raw1 = s.save_raw()
+    lam1_t = torch.tensor(lam1, dtype=torch.float32, device="cuda")
+    dg = torch.zeros((3,) + case.shape, dtype=torch.float32, device="cuda")
+    lam0 = s.adjoint_step(raw0, raw1, lam1_t, dg).double().cpu().numpy()
+    dg = dg.double().cpu().numpy()
+    s.close()
+    want_lam, want_dg = oracle.adjoint_step(G, st0, lam1, g)
+    assert _rel(lam0, want_lam) < 1e-5
+    assert _rel(dg, want_dg) < 1e-5

@@ -17,7 +17,7 @@ from helpers import abs_err, from_device_state, gpu_solver, oracle_grid, rel_err
 
 pytestmark = pytest.mark.gpu
 
-KERNELS = [0, 1]
+KERNELS = [0, 1, 2]  # tiled, direct, population layout
 EPS32 = float(np.finfo(np.float32).eps)
 
 
@@ -33,9 +33,11 @@ def _gpu():
     torch.cuda.set_device(0)
 
 
+@pytest.mark.parametrize("order", [3, 2])
 @pytest.mark.parametrize("kernel", KERNELS)
-def test_taylor_green_100_steps(kernel):
+def test_taylor_green_100_steps(kernel, order):
     case = W.tgv_case()
+    case.order = order
     st0 = W.to_fp32(W.tgv_state(case.nx, case.extra["u0"]))
     G = oracle_grid(case)
     want = oracle.run(G, st0, case.steps)
@@ -47,7 +49,7 @@ def test_taylor_green_100_steps(kernel):
     s.close()
     e_u = rel_err(got[1:4], want[1:4])
     e_rho = rel_err(got[0], want[0])
-    print("TGV kernel=%d rel err u %.3e rho %.3e" % (kernel, e_u, e_rho))
+    print("TGV kernel=%d order=%d rel err u %.3e rho %.3e" % (kernel, order, e_u, e_rho))
     assert e_u <= 1e-5 and e_rho <= 1e-5
     # decay of the Taylor-Green mode at nu = (tau - 1/2)/3
     mode = st0[1]
@@ -69,12 +71,14 @@ CASES = [
 ]
 
 
+@pytest.mark.parametrize("order", [3, 2])
 @pytest.mark.parametrize("kernel", KERNELS)
 @pytest.mark.parametrize("name,faces", CASES)
-def test_random_state_ragged_grid(kernel, name, faces):
+def test_random_state_ragged_grid(kernel, name, faces, order):
     """Odd sizes that span several tiles with ragged tails, random moments,
-    per-node force field; 1 and then 6 more steps against the oracle."""
-    case = W.Case(name, 71, 37, 23, 0.57, faces=faces)
+    per-node force field; 1 and then 6 more steps against the oracle, for the
+    third-order update and the regularised second-order one."""
+    case = W.Case(name, 71, 37, 23, 0.57, faces=faces, order=order)
     st0 = W.to_fp32(W.random_state(case.shape, seed=101))
     g = W.random_force(case.shape, seed=102, amp=1e-5).astype(np.float32).astype(np.float64)
     G = oracle_grid(case)
@@ -188,3 +192,124 @@ def test_determinism(kernel):
         outs.append(s.get_state().cpu().numpy())
         s.close()
     assert np.array_equal(outs[0], outs[1])
+
+
+def test_second_order_update_has_no_adjoint():
+    """The adjoint calls reject the regularised second-order update."""
+    import torch
+    from paper_2401_17074_amd import _binding as C
+    case = W.Case("order2", 16, 12, 10, 0.6, order=2)
+    s = gpu_solver(case)
+    raw = s.save_raw()
+    lam = torch.zeros((10,) + case.shape, dtype=torch.float32, device="cuda")
+    with pytest.raises(RuntimeError, match="third-order"):
+        s.adjoint_step(raw, raw, lam)
+    s.close()
+
+
+@pytest.mark.parametrize("kernel", KERNELS)
+def test_timed_steps_match_plain_steps(kernel):
+    """tslb_step_timed runs the same launches as tslb_step (bit-identical
+    state) and reports positive kernel and auxiliary times."""
+    case = W.channel_case(nx=40, ny=20, nz=18, re_tau=10)
+    st0 = W.to_fp32(W.channel_state(case))
+    out = []
+    for timed in (False, True):
+        s = gpu_solver(case, kernel=kernel)
+        s.set_state(to_device_state(st0))
+        if timed:
+            ms_main, ms_aux = s.step_timed(5)
+            assert ms_main > 0.0 and ms_aux >= 0.0
+        else:
+            s.step(5)
+        assert s.t == 5
+        out.append(s.get_state().cpu().numpy())
+        s.close()
+    assert np.array_equal(out[0], out[1])
+
+
+@pytest.mark.parametrize("kernel", KERNELS)
+@pytest.mark.parametrize("name,faces", CASES[:3])
+def test_relaxation_profile_ragged_grid(kernel, name, faces):
+    """A relaxation time that changes from plane to plane (each population
+    relaxes with the tau of its emitting node's plane): 1 and 6 more steps
+    against the oracle."""
+    case = W.Case(name, 67, 29, 23, 0.57, faces=faces)
+    tau_z = [float(np.float32(v)) for v in np.random.default_rng(104).uniform(0.52, 1.6, case.nz)]
+    st0 = W.to_fp32(W.random_state(case.shape, seed=105))
+    g = W.random_force(case.shape, seed=106, amp=1e-5).astype(np.float32).astype(np.float64)
+    G = oracle.make_grid(case.nx, case.ny, case.nz, float(np.float32(case.tau)), faces=faces, tau_z=tau_z)
+    kinds = oracle.node_kinds(G)
+    fl = kinds == 0
+    s = gpu_solver(case, kernel=kernel)
+    s.set_relaxation_profile(tau_z)
+    s.set_force_field(g)
+    s.set_state(to_device_state(st0))
+    s.step(1)
+    got1 = from_device_state(s.get_state())
+    want1 = oracle.step(G, st0, g)
+    assert abs_err(got1[0], want1[0], fl) < 1e-7
+    assert rel_err(got1[1:4], want1[1:4], fl) < 2e-6
+    assert abs_err(got1[4:], want1[4:], fl) < pi_tol(want1[:, fl])
+    s.step(6)
+    got = from_device_state(s.get_state())
+    # back to the uniform tau: the next step matches the scalar-tau oracle
+    s.set_relaxation_profile(None)
+    s.step(1)
+    got8 = from_device_state(s.get_state())
+    s.close()
+    want = oracle.run(G, st0, 7, g)
+    assert rel_err(got[1:4], want[1:4], fl) < 1e-5
+    assert abs_err(got[0], want[0], fl) < 1e-6
+    G0 = oracle.make_grid(case.nx, case.ny, case.nz, float(np.float32(case.tau)), faces=faces)
+    want8 = oracle.step(G0, got, g, t=7)
+    assert rel_err(got8[1:4], want8[1:4], fl) < 2e-6
+
+
+@pytest.mark.parametrize("kernel", KERNELS)
+def test_small_paper_jet(kernel):
+    """The jet as the paper sets it up, scaled down: inlet disc on z = 0 with
+    time-varying Gaussian noise, periodic crossflow faces, outflow on top and
+    an outlet sponge; 30 steps against the oracle."""
+    case = W.paper_jet_case(nx=30, ny=28, nz=40, D=8.0, steps=30, sponge=(1000.0, 3.0, 10))
+    st0 = W.jet_state(case)
+    G = oracle_grid(case)
+    st0 = oracle.ghost_fill(G, st0, 0)
+    kinds = oracle.node_kinds(G)
+    s = gpu_solver(case, kernel=kernel)
+    s.set_state(to_device_state(st0))
+    got0 = from_device_state(s.get_state())
+    # inlet ghosts at level 0 carry the imposed velocity and the Gaussian noise
+    assert abs_err(got0[1:4], st0[1:4], kinds == 2) < 1e-8
+    s.step(case.steps)
+    got = from_device_state(s.get_state())
+    s.close()
+    want = oracle.run(G, st0, case.steps)
+    assert rel_err(got[1:4], want[1:4]) < 1e-5
+    assert abs_err(got[0], want[0]) < 1e-6
+
+
+def test_paper_jet_full_size_sampled():
+    """440x440x600 jet of the paper's set-up in the benchmark launch (tiled
+    kernel): 10 steps, then one step checked at sampled fluid nodes (several
+    inside the sponge), and the Gaussian inlet refill on the whole inlet face."""
+    case = W.paper_jet_case()
+    s = gpu_solver(case)
+    s.set_state(to_device_state(W.jet_state(case)))
+    s.step(10)
+    pre = from_device_state(s.get_state())
+    s.step(1)
+    post = from_device_state(s.get_state())
+    s.close()
+    G = oracle_grid(case)
+    kinds = oracle.node_kinds(G)
+    idx = W.sample_nodes(case, 3000, 7, fluid_mask=(kinds == 0))
+    top = np.flatnonzero((kinds == 0).ravel()[-60 * case.nx * case.ny:]) + (case.nz - 60) * case.nx * case.ny
+    idx = np.concatenate([idx, np.random.default_rng(8).choice(top, 500, replace=False)])
+    want = oracle.update_nodes(G, pre, idx)
+    got = post.reshape(10, -1)[:, idx]
+    assert np.abs(got[0] - want[0]).max() < 1e-7
+    assert np.abs(got[1:4] - want[1:4]).max() < 2e-6 * max(np.abs(want[1:4]).max(), 1e-3)
+    inlet = post[:, 0]
+    regen = oracle.ghost_fill(G, post, 11)[:, 0]
+    assert np.abs(regen - inlet).max() < 1e-8

@@ -35,6 +35,9 @@ class Case:
     inlet_noise: float = 0.0
     seed: int = 0
     steps: int = 100
+    order: int = 3  # Hermite order of the rebuilt populations (2: regularised collision)
+    noise_kind: int = 0  # inlet perturbation: 0 uniform, 1 Gaussian
+    sponge: tuple = ()  # (K, power, width) of an outlet sponge on the +z face, or ()
     extra: dict = field(default_factory=dict)
 
     @property
@@ -125,6 +128,34 @@ def jet_case(nx=512, ny=256, nz=256, U=0.05, D=20.0, re=7000.0, steps=2000, seed
 
 def jet_state(case):
     return rest_state(case.shape)
+
+
+# --------------------------------------------------------------------------
+# The jet as the paper sets it up (Section 3.2): 440 x 440 x 600, inlet disc
+# D = 20 centred on the z = 0 face with U = 0.05 along z and time-varying
+# Gaussian noise, periodic crossflow faces, outflow at the top, and a sponge
+# of the last 50 planes where nu grows as nu (1 + K xi^3), K = 1000.
+def paper_jet_case(nx=440, ny=440, nz=600, U=0.05, D=20.0, re=7000.0, steps=2000, seed=4321, noise=0.02,
+                   sponge=(1000.0, 3.0, 50)):
+    tau = 0.5 + 3.0 * U * D / re
+    return Case("paper_jet_%dx%dx%d" % (nx, ny, nz), nx, ny, nz, tau,
+                faces=(PERIODIC, PERIODIC, PERIODIC, PERIODIC, INLET, OUTLET),
+                inlet_u=(0.0, 0.0, U), inlet_center=((nx - 1) / 2.0, (ny - 1) / 2.0),
+                inlet_radius=D / 2.0, inlet_noise=noise, seed=seed, steps=steps, noise_kind=1, sponge=sponge)
+
+
+def tau_profile(case):
+    """Relaxation time of each z plane for a case with an outlet sponge, else
+    None.  With nu = (tau - 1/2)/3, the planes z >= z_s = nz - 1 - width get
+    nu_s = nu (1 + K xi^p), xi = (z - z_s) / width in [0, 1]."""
+    if not case.sponge:
+        return None
+    K, pw, width = case.sponge
+    nu = (case.tau - 0.5) / 3.0
+    z = np.arange(case.nz, dtype=np.float64)
+    zs = case.nz - 1 - width
+    xi = np.clip((z - zs) / width, 0.0, 1.0)
+    return 0.5 + 3.0 * nu * (1.0 + K * xi ** pw)
 
 
 # --------------------------------------------------------------------------
