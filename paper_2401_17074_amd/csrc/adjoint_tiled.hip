@@ -274,7 +274,7 @@ hipError_t launch_t(const float* st0, const float* st1, const float* lam1, float
                     const StepParams& p, hipStream_t s) {
     const int tiles_x = (p.geo.n[0] + TX - 1) / TX;
     const int tiles_y = (p.geo.n[1] + TY - 1) / TY;
-    const int TZ = choose_tz(tiles_x * tiles_y, p.geo.n[2], compute_units());
+    const int TZ = choose_tz(tiles_x * tiles_y, p.geo.n[2], compute_units() * kBlocksPerCu);
     const int tiles_z = (p.geo.n[2] + TZ - 1) / TZ;
     const unsigned nblk = (unsigned)tiles_x * tiles_y * tiles_z;
     if (p.geo.N >= (1LL << 30)) return hipErrorInvalidValue;

@@ -27,6 +27,9 @@ namespace tile {
 #ifndef TSLB_EARLY_PREFETCH
 #define TSLB_EARLY_PREFETCH 0
 #endif
+#ifndef TSLB_PREFETCH_DEPTH
+#define TSLB_PREFETCH_DEPTH 1
+#endif
 constexpr int TX = TSLB_TILE_X;              // interior tile width (64: one wave per row)
 constexpr int TY = TSLB_TILE_Y;              // interior rows
 constexpr int LX = TX + 2, LY = TY + 2;      // LDS tile with halo
@@ -297,6 +300,15 @@ inline int choose_tz(int columns, int nz, int cus) {
     }
     return best;
 }
+
+// Blocks of the tiled kernels that one CU holds at once: bounded by LDS
+// (160 KB per CU) and by the waves the register budget allows (4 SIMDs x
+// TSLB_WAVES_PER_EU waves).
+constexpr int kLdsBytes = NBUF * NSLOT * LY * LX * 4;
+constexpr int kBlocksPerCu = (163840 / kLdsBytes) < ((4 * TSLB_WAVES_PER_EU) / (NTHREADS / 64))
+                                 ? (163840 / kLdsBytes)
+                                 : ((4 * TSLB_WAVES_PER_EU) / (NTHREADS / 64));
+static_assert(kBlocksPerCu >= 1, "a tile must fit one CU");
 
 inline int compute_units() {
     static int cus = 0;

@@ -113,6 +113,12 @@ __global__ void __launch_bounds__(NTHREADS, TSLB_WAVES_PER_EU) update_tiled_kern
 
     float mcur[10];
     if (active) load_node<S>(f, col + plane_nodes * (unsigned)plane_index(zs - 1, nz, pz), p, mcur);
+    // With a prefetch depth of 2 the moments of plane zp + 1 are already in
+    // registers (m_ahead) while plane zp is processed, and the loads of plane
+    // zp + 2 are issued: twice the bytes in flight per thread.
+    float m_ahead[10];
+    if (TSLB_PREFETCH_DEPTH == 2 && active)
+        load_node<S>(f, col + plane_nodes * (unsigned)plane_index(zs, nz, pz), p, m_ahead);
 
     // One plane zp with moments mcur: prefetch the next plane into mnext,
     // build and publish this plane's populations, add what arrives from it
@@ -123,7 +129,7 @@ __global__ void __launch_bounds__(NTHREADS, TSLB_WAVES_PER_EU) update_tiled_kern
         float(&lds)[NSLOT][LY][LX] = lds_all[NBUF == 2 ? ((zp - zs + 1) & 1) : 0];
         float mnext[10];
         const bool have_next = zp + 1 <= ze;
-        if (TSLB_EARLY_PREFETCH && active && have_next)
+        if (TSLB_PREFETCH_DEPTH == 1 && TSLB_EARLY_PREFETCH && active && have_next)
             load_node<S>(f, col + plane_nodes * (unsigned)plane_index(zp + 1, nz, pz), p, mnext);
 
         float G[27];
@@ -149,8 +155,12 @@ __global__ void __launch_bounds__(NTHREADS, TSLB_WAVES_PER_EU) update_tiled_kern
             });
             // prefetch the next plane once this plane's moments are consumed;
             // the loads are in flight across the exchange and the gather
-            if (!TSLB_EARLY_PREFETCH && have_next)
-                load_node<S>(f, col + plane_nodes * (unsigned)plane_index(zp + 1, nz, pz), p, mnext);
+            // (mcur is dead once the coefficients are formed, so the next
+            // plane's moments go straight into it: no register copies)
+            if (TSLB_PREFETCH_DEPTH == 1 && !TSLB_EARLY_PREFETCH && have_next)
+                load_node<S>(f, col + plane_nodes * (unsigned)plane_index(zp + 1, nz, pz), p, mcur);
+            if (TSLB_PREFETCH_DEPTH == 2 && zp + 2 <= ze)
+                load_node<S>(f, col + plane_nodes * (unsigned)plane_index(zp + 2, nz, pz), p, mnext);
         }
         __syncthreads();
         if (interior) {
@@ -200,7 +210,13 @@ __global__ void __launch_bounds__(NTHREADS, TSLB_WAVES_PER_EU) update_tiled_kern
                 for (int q = 4; q < 10; ++q) store_out(at(f.out[q], on), S::store(m[q], p.scale[2]));
             }
         }
-        if (have_next) {
+        if (TSLB_PREFETCH_DEPTH == 2) {
+#pragma unroll
+            for (int q = 0; q < 10; ++q) {
+                mcur[q] = m_ahead[q];
+                m_ahead[q] = mnext[q];
+            }
+        } else if (TSLB_EARLY_PREFETCH && have_next) {
 #pragma unroll
             for (int q = 0; q < 10; ++q) mcur[q] = mnext[q];
         }
@@ -286,7 +302,7 @@ template <class S, bool WALLS, bool FIELD, int ORDER>
 hipError_t launch_t(const void* in, void* out, const StepParams& p, hipStream_t s) {
     const int tiles_x = (p.geo.n[0] + TX - 1) / TX;
     const int tiles_y = (p.geo.n[1] + TY - 1) / TY;
-    const int TZ = choose_tz(tiles_x * tiles_y, p.geo.n[2], compute_units());
+    const int TZ = choose_tz(tiles_x * tiles_y, p.geo.n[2], compute_units() * kBlocksPerCu);
     const int tiles_z = (p.geo.n[2] + TZ - 1) / TZ;
     const unsigned nblk = (unsigned)tiles_x * tiles_y * tiles_z;
     if (p.geo.N >= (1LL << 30)) return hipErrorInvalidValue;  // 32-bit node offsets
