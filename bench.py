@@ -27,12 +27,16 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 BYTES_PER_FIELD = {0: 4, 1: 2, 2: 2}
 
 
+# the sources the tiled update kernel is compiled from: HBM counters taken
+# with other sources are not reported as this kernel's traffic
+KERNEL_SOURCES = ("update_tiled.hip", "tslb_tiles.h", "tslb_device.h", "tslb_internal.h")
+
+
 def _source_hash():
     h = hashlib.sha256()
     d = os.path.join(ROOT, "paper_2401_17074_amd", "csrc")
-    for name in sorted(os.listdir(d)):
-        if name.endswith((".hip", ".h")):
-            h.update(open(os.path.join(d, name), "rb").read())
+    for name in KERNEL_SOURCES:
+        h.update(open(os.path.join(d, name), "rb").read())
     return h.hexdigest()[:16]
 
 
@@ -45,10 +49,12 @@ def _fluid_nodes(case):
 
 
 def algorithmic_bytes(case, storage):
-    """Bytes one update launch must move: read the ten stored fields of
-    every node once, write the ten fields of every fluid node once."""
+    """Bytes one update launch must move: read the stored fields of every
+    node once, write those of every fluid node once (ten fields for D3Q27,
+    six for D2Q9)."""
     b = BYTES_PER_FIELD[storage]
-    return 10 * b * case.nodes + 10 * b * _fluid_nodes(case)
+    nf = 6 if case.lattice == 9 else 10
+    return nf * b * case.nodes + nf * b * _fluid_nodes(case)
 
 
 def time_steps(solver, steps, warmup):
@@ -74,7 +80,7 @@ def _solver(case, storage=0, kernel=0, order=3):
     s = Solver(case.nx, case.ny, case.nz, f32(case.tau), force=[f32(v) for v in case.force], faces=case.faces,
                storage=storage, inlet_u=case.inlet_u, inlet_center=case.inlet_center,
                inlet_radius=case.inlet_radius, inlet_noise=case.inlet_noise, seed=case.seed, kernel=kernel,
-               order=order, inlet_noise_kind=case.noise_kind)
+               order=order, inlet_noise_kind=case.noise_kind, lattice=case.lattice)
     prof = W.tau_profile(case)
     if prof is not None:
         s.set_relaxation_profile([f32(v) for v in prof])
@@ -247,6 +253,7 @@ WORKLOADS = {
     "channel512": lambda W: (lambda c: (c, W.channel_state(c)))(W.channel_case(nx=512, ny=256, nz=256)),
     "jet": lambda W: (lambda c: (c, W.jet_state(c)))(W.jet_case()),
     "paper_jet": lambda W: (lambda c: (c, W.jet_state(c)))(W.paper_jet_case()),
+    "channel2d": lambda W: (lambda c: (c, W.channel2d_state(c)))(W.channel2d_case()),
     "cube512": lambda W: (lambda c: (c, W.tgv_state(c.nx, 0.01)))(W.tgv_case(n=512)),
     "tgv32": lambda W: (lambda c: (c, W.tgv_state(c.nx, 0.01)))(W.tgv_case()),
 }
@@ -269,6 +276,28 @@ def measure_workloads(names, steps, warmup, kernel):
                           "kernel_ms": round(kms / steps, 5), "hbm_gbs": round(gbs, 1),
                           "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
     return {"steps": steps, **out}
+
+
+def measure_stats_cost(case, st, samples):
+    """Cost of one statistics sample on the device (profile sums along y and
+    per-node FP64 sums), event-timed over `samples` samples of the state."""
+    import torch
+    s = _solver(case, 0, 0)
+    s.set_state(st)
+    out = {}
+    for name, kw in (("profile", {"profile_axis": 1}), ("field", {"field": True})):
+        s.stats_begin(**kw)
+        s.stats_sample()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(samples):
+            s.stats_sample()
+        e1.record()
+        torch.cuda.synchronize()
+        out[name + "_ms_per_sample"] = round(e0.elapsed_time(e1) / samples, 5)
+    s.close()
+    return {"workload": case.name, "samples": samples, **out}
 
 
 def measure_order_variants(case, st, steps, warmup, kernel):
@@ -357,7 +386,7 @@ def main():
     _, rc = s.reduce(check=False)
     s.close()
     mlups = case.nodes * args.steps / (ms * 1e-3) / 1e6
-    kname = ("update_tiled", "update_direct", "push")[args.kernel]
+    kname = "update_d2q9" if case.lattice == 9 else ("update_tiled", "update_direct", "push")[args.kernel]
     per_launch_s = kms * 1e-3 / n_timed
     algo = algorithmic_bytes(case, 0)
     achieved = algo / per_launch_s / 1e9
@@ -374,7 +403,8 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": case.name, "nodes": case.nodes, "lattice": "D3Q27", "tau": case.tau,
+        "config": {"workload": case.name, "nodes": case.nodes, "lattice": "D2Q9" if case.lattice == 9 else "D3Q27",
+                   "tau": case.tau,
                    "storage": "fp32", "faces": list(case.faces), "kernel": kname, "stable": rc == 0},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
@@ -387,7 +417,8 @@ def main():
         rec["storage_variants"] = measure_storage_variants(200, 10, args.kernel)
         rec["order_variants"] = measure_order_variants(case, _device_state(st64), 200, 10, args.kernel)
         rec["layout_variants"] = measure_layout_variants(case, _device_state(st64), 200, 10)
-        rec["other_workloads"] = measure_workloads(["cube512", "jet", "paper_jet"], 100, 5, args.kernel)
+        rec["other_workloads"] = measure_workloads(["cube512", "jet", "paper_jet", "channel2d"], 100, 5, args.kernel)
+        rec["statistics"] = measure_stats_cost(case, _device_state(st64), 50)
         rec["adjoint"] = measure_adjoint(args.kernel)
         if not args.no_cpu:
             rec["cpu_baseline"] = cpu_baseline(case, st64)

@@ -42,11 +42,12 @@ extern "C" {
 
 typedef struct tslb_ctx *tslb_handle; /* opaque, owned by the library */
 
-enum { TSLB_D3Q27 = 27 };                                   /* the only lattice (Section 2.1) */
+enum { TSLB_D3Q27 = 27, TSLB_D2Q9 = 9 };                    /* lattices (Section 2.1; D2Q9 = 2D counterpart) */
 enum { TSLB_FP32 = 0, TSLB_FP16 = 1, TSLB_BF16 = 2 };       /* moment storage; compute is FP32 */
 enum { TSLB_PERIODIC = 0, TSLB_WALL = 1, TSLB_INLET = 2, TSLB_OUTLET = 3 }; /* face kinds */
 enum { TSLB_DEVICE = 1, TSLB_RHO_DEVIATION = 2 };           /* set/get flags */
 enum { TSLB_OBJ_KINETIC_ENERGY = 0 };                       /* adjoint objectives */
+enum { TSLB_STATS_PROFILE = 1, TSLB_STATS_FIELD = 2 };      /* statistics kinds (bit set) */
 enum {
     TSLB_OK = 0,
     TSLB_E_INVALID = -1,     /* bad argument (tau <= 1/2, dims, unpaired periodic faces, ...) */
@@ -100,13 +101,18 @@ typedef struct {
     int inlet_noise_kind;
 } tslb_bc;
 
-/* Create a solver on an nx*ny*nz grid (Section 2.2 update, D3Q27 only).
+/* Create a solver on an nx*ny*nz grid (Section 2.2 update).
+ * lattice: TSLB_D3Q27, or TSLB_D2Q9 (the two-dimensional counterpart: the
+ *   same reconstruction on the nine-velocity tensor-product lattice; needs
+ *   nz = 1, periodic z faces and zero z components of force and inlet
+ *   velocity; the state keeps the ten-field layout with u_z and the Pi
+ *   components xz, yz, zz held at zero; one update kernel, no adjoint).
  * tau: relaxation time, nu = (tau - 1/2) / 3 (Section 2), must exceed 1/2.
  * force: uniform body acceleration g (Section 3.1 forcing), may be NULL (0).
  * bc: may be NULL (all faces periodic, FP32 storage).
  * Allocates two state buffers on the current HIP device, sets the rest
  * state rho = 1, u = 0, Pi^neq = 0 at level t = 0, and synchronises.
- * Errors: TSLB_E_INVALID, TSLB_E_UNSUPPORTED (lattice != 27), TSLB_E_NOMEM. */
+ * Errors: TSLB_E_INVALID, TSLB_E_UNSUPPORTED (other lattices), TSLB_E_NOMEM. */
 int tslb_create(int nx, int ny, int nz, int lattice, float tau, const float force[3], const tslb_bc *bc,
                 tslb_handle *out);
 
@@ -203,6 +209,46 @@ size_t tslb_rollout_workspace_bytes(tslb_handle h, int nsteps, int every);
 int tslb_rollout_forward(tslb_handle h, int nsteps, int every, void *ws, size_t ws_bytes, void *stream);
 int tslb_rollout_backward(tslb_handle h, int nsteps, int every, void *ws, size_t ws_bytes, float *lam,
                           float *dg_accum, void *stream);
+
+/* Velocity statistics of the turbulence benchmarks, accumulated on the
+ * device in FP64 (Section 3.1: averages over the homogeneous directions and
+ * time; Section 3.2: time averages of the jet).
+ *  kinds  TSLB_STATS_PROFILE: for every index j along `axis` (0 x, 1 y,
+ *         2 z), sums over the fluid nodes of plane j of 1, u_x, u_y, u_z,
+ *         the products u_a u_b in the order xx, yy, zz, xy, xz, yz, and
+ *         u_x^3, u_y^3, u_z^3 (13 values per plane, 13 n_axis doubles).
+ *         TSLB_STATS_FIELD: per-node sums of u_a and u_a u_b (9 N doubles).
+ * tslb_stats_begin zeroes the sums and the sample count (allocating on first
+ * use; TSLB_E_NOMEM) and keeps `axis` for PROFILE; tslb_stats_sample adds
+ * the current level as one sample (asynchronous).  The central moments
+ * <u'_a u'_b> = <u_a u_b> - U_a U_b and <u'^3> = <u^3> - 3 U <u^2> + 2 U^3
+ * follow from the sums; S_2 = <u'u'>/u_tau^2 and S_3 = <u'^3>/<u'^2>^(3/2)
+ * as in Section 3.1.  Errors: TSLB_E_INVALID (kinds 0 or unknown, axis out
+ * of range, no sample yet for the read calls).                               */
+int tslb_stats_begin(tslb_handle h, int kinds, int axis, void *stream);
+int tslb_stats_sample(tslb_handle h, void *stream);
+
+/* Profile sums (host array of 13 n_axis doubles, row j = plane j) and the
+ * number of samples (may be NULL).  Synchronises the stream.                */
+int tslb_stats_profile(tslb_handle h, double *sums, int64_t *nsamples, void *stream);
+
+/* From the FIELD sums: per-node means <u_a> (3N floats, SoA) and
+ * covariances <u'_a u'_b> (6N floats, xx, yy, zz, xy, xz, yz), written to
+ * device memory; either pointer may be NULL.  Asynchronous.                 */
+int tslb_stats_field(tslb_handle h, float *mean_u, float *cov, void *stream);
+
+/* Jet diagnostics from the FIELD means (Section 3.2): for every
+ * cross-section j along `axis`, the nodes are grouped by k = floor(r), r
+ * their distance to the axis point `center` (its two transverse
+ * coordinates in x, y, z order, inside the cross-section); bin k has mean
+ * radius rbar_k and mean axial velocity P_k.  uc[j] = P_0 (the centreline
+ * velocity: nodes within one spacing of the axis) and rhalf[j] = the
+ * half-width, interpolated linearly between the first bin k >= 1 with
+ * P_k <= uc[j] / 2 and the nearest non-empty bin before it (-1 if none).
+ * uc and rhalf are device arrays of n_axis floats.  Asynchronous.
+ * Errors: TSLB_E_INVALID (no FIELD samples, centre outside the
+ * cross-section, cross-section too wide for the LDS bins).                  */
+int tslb_stats_jet(tslb_handle h, int axis, const float center[2], float *uc, float *rhalf, void *stream);
 
 /* Kernel selection for the update and the adjoint step:
  *  0  the LDS-tiled z-marching kernels (default);

@@ -47,6 +47,7 @@ class Grid(ctypes.Structure):
         ("order", ctypes.c_int),
         ("noise_kind", ctypes.c_int),
         ("tau_z", ctypes.POINTER(ctypes.c_double)),
+        ("lattice", ctypes.c_int),
     ]
 
     @property
@@ -60,12 +61,16 @@ class Grid(ctypes.Structure):
 
 def make_grid(nx, ny, nz, tau, faces=(PERIODIC,) * 6, force=(0.0, 0.0, 0.0), inlet_u=(0.0, 0.0, 0.0),
               inlet_center=(0.0, 0.0), inlet_radius=0.0, inlet_noise=0.0, seed=0, order=3, noise_kind=0,
-              tau_z=None):
+              tau_z=None, lattice=27):
     """order: 3 = the recursive third-order update (Section 2.2), 2 = the
     regularised second-order update (Eq. (fullstrcoll)).
     noise_kind: inlet perturbation, 0 uniform in [-1, 1), 1 standard Gaussian.
     tau_z: optional relaxation time per z plane (nz values; the outlet sponge
-    of Section 3.2); every node relaxes with the value of its own plane."""
+    of Section 3.2); every node relaxes with the value of its own plane.
+    lattice: 27 (D3Q27) or 9 (D2Q9: nz = 1 with periodic z faces; the state
+    keeps ten fields, u_z and the Pi components with a z index are zero)."""
+    if lattice == 9:
+        assert nz == 1 and faces[4] == PERIODIC and faces[5] == PERIODIC
     g = Grid()
     g.nx, g.ny, g.nz = nx, ny, nz
     for k in range(6):
@@ -80,6 +85,7 @@ def make_grid(nx, ny, nz, tau, faces=(PERIODIC,) * 6, force=(0.0, 0.0, 0.0), inl
     g.seed = seed
     g.order = order
     g.noise_kind = noise_kind
+    g.lattice = lattice
     if tau_z is not None:
         arr = np.ascontiguousarray(tau_z, dtype=np.float64)
         assert arr.shape == (nz,)
@@ -102,12 +108,12 @@ def _load():
     lib = ctypes.CDLL(_LIB_PATH)
     G = ctypes.POINTER(Grid)
     sig = {
-        "or_lattice": (None, [ctypes.POINTER(ctypes.c_int), _D, ctypes.POINTER(ctypes.c_int)]),
-        "or_hermite": (ctypes.c_double, [ctypes.c_int] * 5),
-        "or_feq": (ctypes.c_double, [ctypes.c_int, ctypes.c_double, _D, ctypes.c_int]),
-        "or_fneq": (ctypes.c_double, [ctypes.c_int, _D, _D, ctypes.c_int]),
-        "or_fpost": (ctypes.c_double, [ctypes.c_int, _D, _D, ctypes.c_double, ctypes.c_int]),
-        "or_moments": (None, [_D, _D]),
+        "or_lattice": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(ctypes.c_int), _D, ctypes.POINTER(ctypes.c_int)]),
+        "or_hermite": (ctypes.c_double, [ctypes.c_int] * 6),
+        "or_feq": (ctypes.c_double, [ctypes.c_int, ctypes.c_int, ctypes.c_double, _D, ctypes.c_int]),
+        "or_fneq": (ctypes.c_double, [ctypes.c_int, ctypes.c_int, _D, _D, ctypes.c_int]),
+        "or_fpost": (ctypes.c_double, [ctypes.c_int, ctypes.c_int, _D, _D, ctypes.c_double, ctypes.c_int]),
+        "or_moments": (None, [ctypes.c_int, _D, _D]),
         "or_node_kind": (ctypes.c_int, [G, ctypes.c_long]),
         "or_node_kinds": (None, [G, ctypes.c_void_p]),
         "or_ghost_fill": (None, [G, _D, ctypes.c_long]),
@@ -159,40 +165,42 @@ def _field(grid, g):
     return g
 
 
-def lattice():
+def lattice(lattice=27):
+    """(c (q, 3), w (q,), opp (q,)) of lattice 27 (D3Q27) or 9 (D2Q9)."""
     lib = _load()
     c = (ctypes.c_int * 81)()
     w = (ctypes.c_double * 27)()
     opp = (ctypes.c_int * 27)()
-    lib.or_lattice(c, w, opp)
-    return np.array(c[:], dtype=np.int64).reshape(27, 3), np.array(w[:]), np.array(opp[:], dtype=np.int64)
+    q = lib.or_lattice(lattice, c, w, opp)
+    return (np.array(c[:3 * q], dtype=np.int64).reshape(q, 3), np.array(w[:q]),
+            np.array(opp[:q], dtype=np.int64))
 
 
-def hermite(i, order, a=0, b=0, g=0):
-    return _load().or_hermite(i, order, a, b, g)
+def hermite(i, order, a=0, b=0, g=0, lattice=27):
+    return _load().or_hermite(lattice, i, order, a, b, g)
 
 
-def feq(i, rho, u, order=3):
+def feq(i, rho, u, order=3, lattice=27):
     u = np.ascontiguousarray(u, dtype=np.float64)
-    return _load().or_feq(i, rho, _p(u), order)
+    return _load().or_feq(lattice, i, rho, _p(u), order)
 
 
-def fneq(i, pi6, u, order=3):
+def fneq(i, pi6, u, order=3, lattice=27):
     pi6 = np.ascontiguousarray(pi6, dtype=np.float64)
     u = np.ascontiguousarray(u, dtype=np.float64)
-    return _load().or_fneq(i, _p(pi6), _p(u), order)
+    return _load().or_fneq(lattice, i, _p(pi6), _p(u), order)
 
 
-def fpost(i, m, g, omega, order=3):
+def fpost(i, m, g, omega, order=3, lattice=27):
     m = np.ascontiguousarray(m, dtype=np.float64)
     g = np.ascontiguousarray(g, dtype=np.float64)
-    return _load().or_fpost(i, _p(m), _p(g), omega, order)
+    return _load().or_fpost(lattice, i, _p(m), _p(g), omega, order)
 
 
-def moments(f):
+def moments(f, lattice=27):
     f = np.ascontiguousarray(f, dtype=np.float64)
     m = np.zeros(10)
-    _load().or_moments(_p(f), _p(m))
+    _load().or_moments(lattice, _p(f), _p(m))
     return m
 
 

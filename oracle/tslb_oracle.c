@@ -25,53 +25,70 @@
 #include <stdlib.h>
 #include <string.h>
 
-#define NQ 27
+#define NQ 27 /* the most velocities of a supported lattice (D3Q27) */
 static const double CS2 = 1.0 / 3.0; /* lattice sound speed squared, Eq. (lbequil) */
 
 /* ------------------------------------------------------------------ */
-/* D3Q27 lattice (Section 2.1, the D3Q27 figure).  The weights are not
- * printed in the paper; they are the tensor product of the one-dimensional
- * three-point Gauss-Hermite weights W(0) = 2/3, W(+-1) = 1/6, the unique
- * set giving the isotropy the text relies on (sum w c c = cs2 delta up to
- * the sixth-order moment sum w cx^2 cy^2 cz^2 = cs2^3).                     */
-static int OC[NQ][3];
-static double OW[NQ];
-static int OPP[NQ];
+/* Lattices (Section 2.1, the D3Q27 figure; D2Q9 is its two-dimensional
+ * counterpart named in Section 2.2).  The weights are not printed in the
+ * paper; they are the tensor products of the one-dimensional three-point
+ * Gauss-Hermite weights W(0) = 2/3, W(+-1) = 1/6, the unique sets giving
+ * the isotropy the text relies on (sum w c c = cs2 delta up to the
+ * highest-order moment, e.g. sum w cx^2 cy^2 cz^2 = cs2^3 in 3D).  D2Q9
+ * velocities are stored as 3-vectors with c_z = 0.                         */
+typedef struct {
+    int q, d;        /* number of velocities, spatial dimensions */
+    int c[NQ][3];
+    double w[NQ];
+    int opp[NQ];
+} lattice_t;
+
+static lattice_t LAT27, LAT9;
 static const int PI_IDX[3][3] = {{0, 3, 4}, {3, 1, 5}, {4, 5, 2}};
+
+static void build_lattice(lattice_t *L, int d)
+{
+    int i = 0;
+    for (int cx = -1; cx <= 1; cx++)
+        for (int cy = -1; cy <= 1; cy++)
+            for (int cz = (d == 3 ? -1 : 0); cz <= (d == 3 ? 1 : 0); cz++) {
+                L->c[i][0] = cx;
+                L->c[i][1] = cy;
+                L->c[i][2] = cz;
+                double w = 1.0;
+                for (int a = 0; a < d; a++) w *= (L->c[i][a] == 0) ? 2.0 / 3.0 : 1.0 / 6.0;
+                L->w[i] = w;
+                i++;
+            }
+    L->q = i;
+    L->d = d;
+    for (int a = 0; a < L->q; a++)
+        for (int b = 0; b < L->q; b++)
+            if (L->c[a][0] == -L->c[b][0] && L->c[a][1] == -L->c[b][1] && L->c[a][2] == -L->c[b][2]) L->opp[a] = b;
+}
 
 static void lattice_init(void)
 {
     static int done = 0;
     if (done) return;
-    int i = 0;
-    for (int cx = -1; cx <= 1; cx++)
-        for (int cy = -1; cy <= 1; cy++)
-            for (int cz = -1; cz <= 1; cz++) {
-                OC[i][0] = cx;
-                OC[i][1] = cy;
-                OC[i][2] = cz;
-                double w = 1.0;
-                for (int a = 0; a < 3; a++) w *= (OC[i][a] == 0) ? 2.0 / 3.0 : 1.0 / 6.0;
-                OW[i] = w;
-                i++;
-            }
-    for (int a = 0; a < NQ; a++)
-        for (int b = 0; b < NQ; b++)
-            if (OC[a][0] == -OC[b][0] && OC[a][1] == -OC[b][1] && OC[a][2] == -OC[b][2]) OPP[a] = b;
+    build_lattice(&LAT27, 3);
+    build_lattice(&LAT9, 2);
     done = 1;
 }
 
-static double hermite1(int i, int a) { return (double)OC[i][a]; }
+static const lattice_t *lattice_of(int id) { return id == 9 ? &LAT9 : &LAT27; }
 
-static double hermite2(int i, int a, int b)
+static double hermite1(const lattice_t *L, int i, int a) { return (double)L->c[i][a]; }
+
+static double hermite2(const lattice_t *L, int i, int a, int b)
 {
-    return (double)(OC[i][a] * OC[i][b]) - CS2 * (a == b);
+    return (double)(L->c[i][a] * L->c[i][b]) - CS2 * (a == b);
 }
 
-static double hermite3(int i, int a, int b, int g)
+static double hermite3(const lattice_t *L, int i, int a, int b, int g)
 {
-    return (double)(OC[i][a] * OC[i][b] * OC[i][g]) -
-           CS2 * (OC[i][g] * (a == b) + OC[i][a] * (b == g) + OC[i][b] * (a == g));
+    const int *c = L->c[i];
+    return (double)(c[a] * c[b] * c[g]) - CS2 * (c[g] * (a == b) + c[a] * (b == g) + c[b] * (a == g));
 }
 
 /* ------------------------------------------------------------------ */
@@ -92,7 +109,10 @@ typedef struct {
     int order; /* Hermite order of the reconstruction: 3 (Section 2.2) or 2 (Eq. (fullstrcoll)) */
     int noise_kind; /* inlet perturbation: 0 uniform in [-1, 1), 1 standard Gaussian (Section 3.2) */
     const double *tau_z; /* relaxation time of each z plane (the jet's outlet sponge), or NULL: tau */
+    int lattice; /* 27 (or 0): D3Q27; 9: D2Q9 on an nz = 1 grid with periodic z faces */
 } or_grid;
+
+static const lattice_t *lat(const or_grid *G) { return lattice_of(G->lattice); }
 
 static int dim(const or_grid *G, int d) { return d == 0 ? G->nx : (d == 1 ? G->ny : G->nz); }
 static int is_ghost_face(int k) { return k == FACE_INLET || k == FACE_OUTLET; }
@@ -150,7 +170,7 @@ static long upstream(const or_grid *G, const int x[3], int i)
     int y[3];
     for (int d = 0; d < 3; d++) {
         int n = dim(G, d);
-        y[d] = x[d] - OC[i][d];
+        y[d] = x[d] - lat(G)->c[i][d];
         if (G->face[2 * d] == FACE_PERIODIC) y[d] = ((y[d] % n) + n) % n;
         if (y[d] < 0 || y[d] >= n) return -2; /* cannot happen for a fluid node */
     }
@@ -217,9 +237,12 @@ static int inlet_velocity(const or_grid *G, const int x[3], long n, long t, doub
         if (r1 * r1 + r2 * r2 > G->inlet_radius * G->inlet_radius) continue;
         double mag = sqrt(G->inlet_u[0] * G->inlet_u[0] + G->inlet_u[1] * G->inlet_u[1] +
                           G->inlet_u[2] * G->inlet_u[2]);
-        for (int a = 0; a < 3; a++)
-            ub[a] = G->inlet_u[a] + G->inlet_noise * mag *
-                    (G->noise_kind == 1 ? inlet_gauss(G->seed, t, n, N, a) : inlet_xi(G->seed, t, n, N, a));
+        for (int a = 0; a < 3; a++) {
+            ub[a] = G->inlet_u[a];
+            if (a < lat(G)->d)
+                ub[a] += G->inlet_noise * mag *
+                         (G->noise_kind == 1 ? inlet_gauss(G->seed, t, n, N, a) : inlet_xi(G->seed, t, n, N, a));
+        }
         return 1;
     }
     return 0;
@@ -265,54 +288,59 @@ double or_round_bf16(double x) { return round_binary(x, 7, -126, ldexp(255.0, 12
 /* ================================================================== */
 /* Exported API (ctypes).                                              */
 
-void or_lattice(int *c, double *w, int *opp)
+/* Velocities (3 ints each), weights and opposites of lattice 27 or 9;
+ * returns the number of velocities.                                         */
+int or_lattice(int lattice, int *c, double *w, int *opp)
 {
     lattice_init();
-    for (int i = 0; i < NQ; i++) {
-        for (int a = 0; a < 3; a++) c[3 * i + a] = OC[i][a];
-        w[i] = OW[i];
-        opp[i] = OPP[i];
+    const lattice_t *L = lattice_of(lattice);
+    for (int i = 0; i < L->q; i++) {
+        for (int a = 0; a < 3; a++) c[3 * i + a] = L->c[i][a];
+        w[i] = L->w[i];
+        opp[i] = L->opp[i];
     }
+    return L->q;
 }
 
 /* Hermite tensor component of order `order` (0..3) at velocity i. */
-double or_hermite(int i, int order, int a, int b, int g)
+double or_hermite(int lattice, int i, int order, int a, int b, int g)
 {
     lattice_init();
+    const lattice_t *L = lattice_of(lattice);
     switch (order) {
     case 0: return 1.0;
-    case 1: return hermite1(i, a);
-    case 2: return hermite2(i, a, b);
-    case 3: return hermite3(i, a, b, g);
+    case 1: return hermite1(L, i, a);
+    case 2: return hermite2(L, i, a, b);
+    case 3: return hermite3(L, i, a, b, g);
     }
     return NAN;
 }
 
-double or_feq(int i, double rho, const double *u, int order)
+double or_feq(int lattice, int i, double rho, const double *u, int order)
 {
     lattice_init();
-    return feq_r(i, rho, u, order);
+    return feq_r(lattice_of(lattice), i, rho, u, order);
 }
 
-double or_fneq(int i, const double *pi6, const double *u, int order)
+double or_fneq(int lattice, int i, const double *pi6, const double *u, int order)
 {
     lattice_init();
     double pi[3][3];
     for (int a = 0; a < 3; a++)
         for (int b = 0; b < 3; b++) pi[a][b] = pi6[PI_IDX[a][b]];
-    return fneq_r(i, pi, u, order);
+    return fneq_r(lattice_of(lattice), i, pi, u, order);
 }
 
-double or_fpost(int i, const double *m, const double *g, double omega, int order)
+double or_fpost(int lattice, int i, const double *m, const double *g, double omega, int order)
 {
     lattice_init();
-    return fpost_r(i, m, g, omega, order);
+    return fpost_r(lattice_of(lattice), i, m, g, omega, order);
 }
 
-void or_moments(const double *f, double *m)
+void or_moments(int lattice, const double *f, double *m)
 {
     lattice_init();
-    moments_r(f, m);
+    moments_r(lattice_of(lattice), f, m);
 }
 
 int or_node_kind(const or_grid *G, long n) { return node_kind(G, n); }
@@ -378,7 +406,7 @@ void or_update_nodes(const or_grid *G, const double *in, const double *gf, const
     for (long k = 0; k < nidx; k++) {
         double f[NQ], m[10];
         gather_r(G, in, gf, idx[k], f);
-        moments_r(f, m);
+        moments_r(lat(G), f, m);
         for (int q = 0; q < 10; q++) out[q * nidx + k] = m[q];
     }
 }
@@ -449,7 +477,7 @@ static void adjoint_populations(const or_grid *G, const double *st, const double
         double complex fc[NQ], mc[10];
         for (int k = 0; k < NQ; k++) fc[k] = f[k];
         fc[i] += I * CSTEP;
-        moments_c(fc, mc);
+        moments_c(lat(G), fc, mc);
         double s = 0.0;
         for (int q = 0; q < 10; q++) s += lam[q * N + x] * cimag(mc[q]) / CSTEP;
         lf[i] = s;
@@ -471,7 +499,7 @@ static void adjoint_emit(const or_grid *G, const double *st, const double *gf, l
             m[p] += I * CSTEP;
         else
             g[p - 10] += I * CSTEP;
-        double d = cimag(fpost_c(k, m, g, omega, G->order)) / CSTEP;
+        double d = cimag(fpost_c(lat(G), k, m, g, omega, G->order)) / CSTEP;
         if (p < 10)
             lm[p] += d * lf;
         else
@@ -482,7 +510,7 @@ static void adjoint_emit(const or_grid *G, const double *st, const double *gf, l
 /* Reverse-mode sensitivity at node y (gather from the downstream nodes):
  * lam_t(y) = sum over populations emitted by y of J^T lam_f, where y emits
  * population i to y + c_i, and, for each direction whose upstream node is
- * solid, its own bounced-back population OPP[i] to itself.                  */
+ * solid, its own bounced-back population opp(i) to itself.                 */
 static int adjoint_node(const or_grid *G, const double *st, const double *gf, const double *lam1,
                         const double *lf_all, long y, double lm[10], double lg[3])
 {
@@ -495,7 +523,7 @@ static int adjoint_node(const or_grid *G, const double *st, const double *gf, co
         int xd[3], ok = 1;
         for (int d = 0; d < 3; d++) {
             int n = dim(G, d);
-            xd[d] = xy[d] + OC[i][d];
+            xd[d] = xy[d] + lat(G)->c[i][d];
             if (G->face[2 * d] == FACE_PERIODIC) xd[d] = ((xd[d] % n) + n) % n;
             if (xd[d] < 0 || xd[d] >= n) ok = 0;
         }
@@ -514,7 +542,7 @@ static int adjoint_node(const or_grid *G, const double *st, const double *gf, co
                 memcpy(lf, lf_all + (size_t)y * NQ, sizeof lf);
             else
                 adjoint_populations(G, st, gf, lam1, y, lf);
-            adjoint_emit(G, st, gf, y, OPP[i], lf[i], lm, lg);
+            adjoint_emit(G, st, gf, y, lat(G)->opp[i], lf[i], lm, lg);
         }
     }
     return 0;

@@ -12,11 +12,12 @@ import os
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libtslb.so")
 
-TSLB_D3Q27 = 27
+TSLB_D3Q27, TSLB_D2Q9 = 27, 9
 TSLB_FP32, TSLB_FP16, TSLB_BF16 = 0, 1, 2
 TSLB_PERIODIC, TSLB_WALL, TSLB_INLET, TSLB_OUTLET = 0, 1, 2, 3
 TSLB_DEVICE, TSLB_RHO_DEVIATION = 1, 2
 TSLB_OBJ_KINETIC_ENERGY = 0
+TSLB_STATS_PROFILE, TSLB_STATS_FIELD = 1, 2
 TSLB_OK, TSLB_E_INVALID, TSLB_E_UNSUPPORTED, TSLB_E_NOMEM, TSLB_E_HIP, TSLB_E_UNSTABLE = 0, -1, -2, -3, -4, -5
 
 # every symbol include/tslb.h declares, with (restype, argtypes)
@@ -47,6 +48,11 @@ SIGNATURES = {
     "tslb_get_moments": (_i, [_vp, _vp, _vp, _vp, _i, _vp]),
     "tslb_set_force_field": (_i, [_vp, _vp, _vp]),
     "tslb_step": (_i, [_vp, _i, _vp]),
+    "tslb_stats_begin": (_i, [_vp, _i, _i, _vp]),
+    "tslb_stats_sample": (_i, [_vp, _vp]),
+    "tslb_stats_profile": (_i, [_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64), _vp]),
+    "tslb_stats_field": (_i, [_vp, _vp, _vp, _vp]),
+    "tslb_stats_jet": (_i, [_vp, _i, _fp, _vp, _vp, _vp]),
     "tslb_set_relaxation_profile": (_i, [_vp, _fp, _vp]),
     "tslb_step_timed": (_i, [_vp, _i, ctypes.POINTER(ctypes.c_double), _vp]),
     "tslb_get_time": (_i64, [_vp]),
@@ -148,6 +154,31 @@ def tslb_set_force_field(h, g, stream=None):
 
 def tslb_step(h, nsteps, stream=None):
     return _check(lib.tslb_step(h, nsteps, _stream(stream)))
+
+
+def tslb_stats_begin(h, kinds, axis=1, stream=None):
+    return _check(lib.tslb_stats_begin(h, kinds, axis, _stream(stream)))
+
+
+def tslb_stats_sample(h, stream=None):
+    return _check(lib.tslb_stats_sample(h, _stream(stream)))
+
+
+def tslb_stats_profile(h, n_axis, stream=None):
+    """Returns (sums as a list of n_axis rows of 13 floats, number of samples)."""
+    buf = (ctypes.c_double * (13 * n_axis))()
+    ns = ctypes.c_int64()
+    _check(lib.tslb_stats_profile(h, buf, ctypes.byref(ns), _stream(stream)))
+    return [list(buf[13 * j:13 * j + 13]) for j in range(n_axis)], ns.value
+
+
+def tslb_stats_field(h, mean_u, cov, stream=None):
+    return _check(lib.tslb_stats_field(h, _ptr(mean_u), _ptr(cov), _stream(stream)))
+
+
+def tslb_stats_jet(h, axis, center, uc, rhalf, stream=None):
+    c = (ctypes.c_float * 2)(*[float(v) for v in center])
+    return _check(lib.tslb_stats_jet(h, axis, c, _ptr(uc), _ptr(rhalf), _stream(stream)))
 
 
 def tslb_set_relaxation_profile(h, tau_z, stream=None):

@@ -6,7 +6,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 SOURCES = ["capi.hip", "aux_kernels.hip", "update_direct.hip", "update_tiled.hip", "adjoint_tiled.hip",
-           "update_poplayout.hip"]
+           "update_poplayout.hip", "stats.hip",
+           "update_d2q9.hip"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++20", "-fPIC", "-Wall",
          # packed FP32 instructions are kept out of every kernel
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]

@@ -64,7 +64,7 @@ __global__ void ghost_fill_kernel(typename S::T* __restrict__ st, StepParams p, 
         const float r1 = (float)c[e1] - q.center[0], r2 = (float)c[e2] - q.center[1];
         if (r1 * r1 + r2 * r2 > q.radius2) continue;
         const uint64_t tn = (uint64_t)t * (uint64_t)g.N + (uint64_t)n;
-        for (int a = 0; a < 3; ++a) {
+        for (int a = 0; a < p.dims; ++a) {
             float xi;
             if (q.noise_kind == 1) {
                 // Box-Muller: sqrt(-2 ln v1) cos(2 pi v2), v1 in (0, 1], v2 in [0, 1)
@@ -98,10 +98,16 @@ __global__ void pack_kernel(const float* __restrict__ rho, const float* __restri
     const float keep = is_solid(g, x, y, z) ? 0.0f : 1.0f;
     const float r = rho[n];
     st[n] = S::store(keep * (rho_dev ? r : r - 1.0f), p.scale[0]);
+    // a two-dimensional lattice keeps u_z and the Pi components with a z
+    // index (zz, xz, yz) at zero
+    const float kz = p.dims == 2 ? 0.0f : keep;
 #pragma unroll
-    for (int a = 0; a < 3; ++a) st[(1 + a) * N + n] = S::store(keep * u[a * N + n], p.scale[1]);
+    for (int a = 0; a < 3; ++a) st[(1 + a) * N + n] = S::store((a == 2 ? kz : keep) * u[a * N + n], p.scale[1]);
 #pragma unroll
-    for (int k = 0; k < 6; ++k) st[(4 + k) * N + n] = S::store(pi ? keep * pi[k * N + n] : 0.0f, p.scale[2]);
+    for (int k = 0; k < 6; ++k) {
+        const float kk = (k == 2 || k == 4 || k == 5) ? kz : keep;
+        st[(4 + k) * N + n] = S::store(pi ? kk * pi[k * N + n] : 0.0f, p.scale[2]);
+    }
 }
 
 template <class S>

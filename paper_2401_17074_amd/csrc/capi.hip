@@ -40,6 +40,7 @@ inline bool ghost_kind(int k) { return k == TSLB_INLET || k == TSLB_OUTLET; }
 
 // The update proper (without the wall fix-up pass of the tiled kernel).
 hipError_t run_main_update(tslb_ctx* h, const void* in, void* out, hipStream_t s) {
+    if (h->lattice == TSLB_D2Q9) return launch_update_d2q9(h->storage, in, out, h->p, s);
     switch (h->kernel) {
     case 0: return launch_update_tiled(h->storage, in, out, h->p, s);
     case 1: return launch_update_direct(h->storage, in, out, h->p, s);
@@ -50,7 +51,7 @@ hipError_t run_main_update(tslb_ctx* h, const void* in, void* out, hipStream_t s
 
 hipError_t run_update(tslb_ctx* h, const void* in, void* out, hipStream_t s) {
     hipError_t e = run_main_update(h, in, out, s);
-    if (e != hipSuccess || h->kernel != 0) return e;
+    if (e != hipSuccess || h->kernel != 0 || h->lattice != TSLB_D3Q27) return e;
     return launch_wall_fixup(h->storage, in, out, h->p, s);
 }
 
@@ -89,7 +90,8 @@ int tslb_create(int nx, int ny, int nz, int lattice, float tau, const float forc
                 tslb_handle* out) {
     if (!out) return fail(TSLB_E_INVALID, "out handle pointer is NULL");
     *out = nullptr;
-    if (lattice != TSLB_D3Q27) return fail(TSLB_E_UNSUPPORTED, "lattice %d: only D3Q27 (27) is provided", lattice);
+    if (lattice != TSLB_D3Q27 && lattice != TSLB_D2Q9)
+        return fail(TSLB_E_UNSUPPORTED, "lattice %d: D3Q27 (27) and D2Q9 (9) are provided", lattice);
     if (nx < 1 || ny < 1 || nz < 1) return fail(TSLB_E_INVALID, "grid dimensions must be >= 1");
     if (!(tau > 0.5f) || !isfinite(tau)) return fail(TSLB_E_INVALID, "tau must exceed 1/2 (got %g)", (double)tau);
     tslb_bc b;
@@ -121,6 +123,9 @@ int tslb_create(int nx, int ny, int nz, int lattice, float tau, const float forc
     if (b.order != 2 && b.order != 3) return fail(TSLB_E_INVALID, "Hermite order %d is not 2 or 3", b.order);
     if (b.inlet_noise_kind != 0 && b.inlet_noise_kind != 1)
         return fail(TSLB_E_INVALID, "inlet noise kind %d is not 0 or 1", b.inlet_noise_kind);
+    if (lattice == TSLB_D2Q9 && (nz != 1 || b.face[4] != TSLB_PERIODIC || b.face[5] != TSLB_PERIODIC ||
+                                 b.inlet_u[2] != 0.0f || (force && force[2] != 0.0f)))
+        return fail(TSLB_E_INVALID, "D2Q9 needs nz = 1, periodic z faces and no z velocity or force");
 
     tslb_ctx* h = new (std::nothrow) tslb_ctx;
     if (!h) return fail(TSLB_E_NOMEM, "host allocation failed");
@@ -141,6 +146,9 @@ int tslb_create(int nx, int ny, int nz, int lattice, float tau, const float forc
     g.N = (long long)nx * ny * nz;
     h->p.one_minus_omega = (float)(1.0 - 1.0 / (double)tau);
     h->p.order = b.order;
+    h->p.dims = lattice == TSLB_D2Q9 ? 2 : 3;
+    h->lattice = lattice;
+    h->stats_prof_axis = -1;
     for (int a = 0; a < 3; ++a) h->p.force[a] = force ? force[a] : 0.0f;
     h->p.gfield = nullptr;
     for (int k = 0; k < 3; ++k) {
@@ -203,6 +211,9 @@ int tslb_destroy(tslb_handle h) {
     (void)hipFree(h->p.wall_side);
     (void)hipFree(h->pop);
     (void)hipFree(h->omo_z);
+    (void)hipFree(h->stats_prof);
+    (void)hipFree(h->stats_part);
+    (void)hipFree(h->stats_field);
     delete h;
     return TSLB_OK;
 }
@@ -210,6 +221,8 @@ int tslb_destroy(tslb_handle h) {
 int tslb_set_kernel(tslb_handle h, int variant) {
     if (!h) return fail(TSLB_E_INVALID, "NULL handle");
     if (variant < 0 || variant > 2) return fail(TSLB_E_INVALID, "kernel variant %d out of range", variant);
+    if (h->lattice != TSLB_D3Q27 && variant != 0)
+        return fail(TSLB_E_UNSUPPORTED, "D2Q9 has one update kernel (variant 0)");
     if (variant == 2 && !h->pop) {
         DeviceGuard dg(h->device);
         const size_t bytes = sizeof(float) * 27 * (size_t)h->p.geo.N;
@@ -308,6 +321,102 @@ int tslb_set_relaxation_profile(tslb_handle h, const float* tau_z, void* stream)
     return TSLB_OK;
 }
 
+int tslb_stats_begin(tslb_handle h, int kinds, int axis, void* stream) {
+    if (!h) return fail(TSLB_E_INVALID, "NULL handle");
+    if (kinds <= 0 || (kinds & ~(TSLB_STATS_PROFILE | TSLB_STATS_FIELD)))
+        return fail(TSLB_E_INVALID, "statistics kinds %d", kinds);
+    if ((kinds & TSLB_STATS_PROFILE) && (axis < 0 || axis > 2)) return fail(TSLB_E_INVALID, "axis %d", axis);
+    DeviceGuard dg(h->device);
+    hipStream_t s = S(stream);
+    const Geometry& g = h->p.geo;
+    if (kinds & TSLB_STATS_PROFILE) {
+        if (h->stats_prof_axis != axis) {
+            (void)hipFree(h->stats_prof);
+            (void)hipFree(h->stats_part);
+            h->stats_prof = nullptr;
+            h->stats_part = nullptr;
+            h->stats_prof_axis = -1;
+            const size_t n_axis = (size_t)g.n[axis];
+            const size_t bpp = (size_t)stats_blocks_per_plane(g, axis);
+            if (hipMalloc((void**)&h->stats_prof, sizeof(double) * 13 * n_axis) != hipSuccess ||
+                hipMalloc((void**)&h->stats_part, sizeof(double) * 13 * n_axis * bpp) != hipSuccess) {
+                (void)hipFree(h->stats_prof);
+                h->stats_prof = nullptr;
+                h->stats_part = nullptr;
+                return fail(TSLB_E_NOMEM, "profile statistics allocation failed");
+            }
+            h->stats_prof_axis = axis;
+        }
+        HIP_TRY(hipMemsetAsync(h->stats_prof, 0, sizeof(double) * 13 * (size_t)g.n[axis], s));
+    }
+    if (kinds & TSLB_STATS_FIELD) {
+        if (!h->stats_field && hipMalloc((void**)&h->stats_field, sizeof(double) * 9 * (size_t)g.N) != hipSuccess) {
+            h->stats_field = nullptr;
+            return fail(TSLB_E_NOMEM, "field statistics allocation of %zu bytes failed",
+                        sizeof(double) * 9 * (size_t)g.N);
+        }
+        HIP_TRY(hipMemsetAsync(h->stats_field, 0, sizeof(double) * 9 * (size_t)g.N, s));
+    }
+    h->stats_kinds = kinds;
+    h->stats_axis = axis;
+    h->stats_samples = 0;
+    return TSLB_OK;
+}
+
+int tslb_stats_sample(tslb_handle h, void* stream) {
+    if (!h) return fail(TSLB_E_INVALID, "NULL handle");
+    if (!h->stats_kinds) return fail(TSLB_E_INVALID, "tslb_stats_begin was not called");
+    DeviceGuard dg(h->device);
+    hipStream_t s = S(stream);
+    if (h->stats_kinds & TSLB_STATS_PROFILE)
+        HIP_TRY(launch_stats_profile(h->storage, h->buf[h->cur], h->stats_part, h->stats_prof, h->p, h->stats_axis, s));
+    if (h->stats_kinds & TSLB_STATS_FIELD)
+        HIP_TRY(launch_stats_field(h->storage, h->buf[h->cur], h->stats_field, h->p, s));
+    h->stats_samples += 1;
+    return TSLB_OK;
+}
+
+int tslb_stats_profile(tslb_handle h, double* sums, int64_t* nsamples, void* stream) {
+    if (!h || !sums) return fail(TSLB_E_INVALID, "NULL handle or output");
+    if (!(h->stats_kinds & TSLB_STATS_PROFILE)) return fail(TSLB_E_INVALID, "profile statistics are not enabled");
+    DeviceGuard dg(h->device);
+    hipStream_t s = S(stream);
+    HIP_TRY(hipMemcpyAsync(sums, h->stats_prof, sizeof(double) * 13 * (size_t)h->p.geo.n[h->stats_axis],
+                           hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (nsamples) *nsamples = h->stats_samples;
+    return TSLB_OK;
+}
+
+int tslb_stats_field(tslb_handle h, float* mean_u, float* cov, void* stream) {
+    if (!h) return fail(TSLB_E_INVALID, "NULL handle");
+    if (!(h->stats_kinds & TSLB_STATS_FIELD) || h->stats_samples < 1)
+        return fail(TSLB_E_INVALID, "no field statistics sampled");
+    DeviceGuard dg(h->device);
+    HIP_TRY(launch_stats_field_moments(h->stats_field, h->p.geo.N, 1.0 / (double)h->stats_samples, mean_u, cov,
+                                       S(stream)));
+    return TSLB_OK;
+}
+
+int tslb_stats_jet(tslb_handle h, int axis, const float center[2], float* uc, float* rhalf, void* stream) {
+    if (!h || !center || !uc || !rhalf) return fail(TSLB_E_INVALID, "NULL argument");
+    if (axis < 0 || axis > 2) return fail(TSLB_E_INVALID, "axis %d", axis);
+    if (!(h->stats_kinds & TSLB_STATS_FIELD) || h->stats_samples < 1)
+        return fail(TSLB_E_INVALID, "no field statistics sampled");
+    const Geometry& g = h->p.geo;
+    const int d1 = axis == 0 ? 1 : 0, d2 = axis == 2 ? 1 : 2;
+    if (!(center[0] >= 0.0f && center[0] <= (float)(g.n[d1] - 1) && center[1] >= 0.0f &&
+          center[1] <= (float)(g.n[d2] - 1)))
+        return fail(TSLB_E_INVALID, "jet centre (%g, %g) outside the cross-section", (double)center[0],
+                    (double)center[1]);
+    if ((size_t)stats_jet_bins(g, axis, center[0], center[1]) * 3 * sizeof(double) > 65536)
+        return fail(TSLB_E_INVALID, "cross-section too wide for the radial bins");
+    DeviceGuard dg(h->device);
+    HIP_TRY(launch_stats_jet(h->stats_field, g, axis, center[0], center[1], 1.0 / (double)h->stats_samples, uc,
+                             rhalf, S(stream)));
+    return TSLB_OK;
+}
+
 int tslb_step(tslb_handle h, int nsteps, void* stream) {
     if (!h) return fail(TSLB_E_INVALID, "NULL handle");
     if (nsteps < 0) return fail(TSLB_E_INVALID, "nsteps must be >= 0");
@@ -344,7 +453,8 @@ int tslb_step_timed(tslb_handle h, int nsteps, double ms[2], void* stream) {
         hipError_t e = hipEventRecord(ev[3 * k], s);
         if (e == hipSuccess) e = run_main_update(h, in, out, s);
         if (e == hipSuccess) e = hipEventRecord(ev[3 * k + 1], s);
-        if (e == hipSuccess && h->kernel == 0) e = launch_wall_fixup(h->storage, in, out, h->p, s);
+        if (e == hipSuccess && h->kernel == 0 && h->lattice == TSLB_D3Q27)
+            e = launch_wall_fixup(h->storage, in, out, h->p, s);
         if (e != hipSuccess) {
             rc = fail(TSLB_E_HIP, "timed step: %s", hipGetErrorString(e));
             break;
@@ -429,6 +539,7 @@ int tslb_adjoint_step(tslb_handle h, const void* state_t, const void* state_t1, 
     if (h->storage != TSLB_FP32) return fail(TSLB_E_UNSUPPORTED, "the adjoint needs FP32 storage");
     if (h->has_ghosts) return fail(TSLB_E_UNSUPPORTED, "the adjoint does not differentiate inlet/outlet ghosts");
     if (h->p.order != 3) return fail(TSLB_E_UNSUPPORTED, "the adjoint differentiates the third-order update only");
+    if (h->lattice != TSLB_D3Q27) return fail(TSLB_E_UNSUPPORTED, "the adjoint is provided for D3Q27 only");
     DeviceGuard dg(h->device);
     if (h->kernel != 1)
         HIP_TRY(launch_adjoint_tiled((const float*)state_t, (const float*)state_t1, lam_t1, lam_t, dg_accum, h->p,
@@ -449,7 +560,8 @@ size_t tslb_rollout_workspace_bytes(tslb_handle h, int nsteps, int every) {
 int tslb_rollout_forward(tslb_handle h, int nsteps, int every, void* ws, size_t ws_bytes, void* stream) {
     if (!h || !ws || nsteps < 1 || every < 1) return fail(TSLB_E_INVALID, "bad rollout arguments");
     if (ws_bytes < tslb_rollout_workspace_bytes(h, nsteps, every)) return fail(TSLB_E_INVALID, "workspace too small");
-    if (h->p.order != 3) return fail(TSLB_E_UNSUPPORTED, "the adjoint differentiates the third-order update only");
+    if (h->p.order != 3 || h->lattice != TSLB_D3Q27)
+        return fail(TSLB_E_UNSUPPORTED, "the adjoint differentiates the third-order D3Q27 update only");
     const size_t sb = tslb_state_bytes(h);
     char* ck = (char*)ws;
     for (int s0 = 0, seg = 0; s0 < nsteps; s0 += every, ++seg) {
@@ -465,7 +577,8 @@ int tslb_rollout_backward(tslb_handle h, int nsteps, int every, void* ws, size_t
                           float* dg_accum, void* stream) {
     if (!h || !ws || !lam || nsteps < 1 || every < 1) return fail(TSLB_E_INVALID, "bad rollout arguments");
     if (ws_bytes < tslb_rollout_workspace_bytes(h, nsteps, every)) return fail(TSLB_E_INVALID, "workspace too small");
-    if (h->p.order != 3) return fail(TSLB_E_UNSUPPORTED, "the adjoint differentiates the third-order update only");
+    if (h->p.order != 3 || h->lattice != TSLB_D3Q27)
+        return fail(TSLB_E_UNSUPPORTED, "the adjoint differentiates the third-order D3Q27 update only");
     DeviceGuard dg(h->device);
     hipStream_t s = S(stream);
     const size_t sb = tslb_state_bytes(h);

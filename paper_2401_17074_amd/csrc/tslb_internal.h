@@ -14,6 +14,7 @@ struct StepParams {
     Geometry geo;
     float one_minus_omega;   // 1 - 1/tau
     int order;               // Hermite order of the rebuilt populations (2 or 3)
+    int dims;                // 3 (D3Q27) or 2 (D2Q9: u_z and the z components of Pi stay zero)
     const float* omo_z;      // optional 1 - omega per z plane (nz floats), else one_minus_omega
     float force[3];          // uniform acceleration (used when gfield == nullptr)
     const float* gfield;     // optional per-node acceleration, 3N SoA
@@ -50,6 +51,16 @@ hipError_t launch_update_direct(int storage, const void* in, void* out, const St
 hipError_t launch_update_poplayout(int storage, const void* in, void* out, float* pop, const StepParams& p,
                                    hipStream_t s);
 hipError_t launch_update_tiled(int storage, const void* in, void* out, const StepParams& p, hipStream_t s);
+hipError_t launch_update_d2q9(int storage, const void* in, void* out, const StepParams& p, hipStream_t s);
+int stats_blocks_per_plane(const Geometry& g, int axis);
+int stats_jet_bins(const Geometry& g, int axis, float c1, float c2);
+hipError_t launch_stats_profile(int storage, const void* st, double* part, double* sums, const StepParams& p,
+                                int axis, hipStream_t s);
+hipError_t launch_stats_field(int storage, const void* st, double* fs, const StepParams& p, hipStream_t s);
+hipError_t launch_stats_field_moments(const double* fs, long long N, double inv_ns, float* mean, float* cov,
+                                      hipStream_t s);
+hipError_t launch_stats_jet(const double* fs, const Geometry& g, int axis, float c1, float c2, double inv_ns,
+                            float* uc, float* rhalf, hipStream_t s);
 // Completes the wall-adjacent nodes after launch_update_tiled (walls only).
 hipError_t launch_wall_fixup(int storage, const void* in, void* out, const StepParams& p, hipStream_t s);
 hipError_t launch_ghost_fill(int storage, void* st, const StepParams& p, const InletParams& q, int64_t t,
@@ -84,7 +95,16 @@ struct tslb_ctx {
     int red_blocks;
     int64_t t;               // current level
     int kernel;              // 0 tiled, 1 direct, 2 population layout
+    int lattice;             // 27 or 9
     float* pop;              // 27 N populations of the population-layout variant (lazily)
     float* omo_z;            // owned per-plane 1 - omega (or null)
+    // velocity statistics (FP64 sums, lazily allocated)
+    int stats_kinds;         // TSLB_STATS_* bits enabled by the last begin
+    int stats_axis;          // profile axis
+    int64_t stats_samples;
+    double* stats_prof;      // 13 n_axis sums
+    double* stats_part;      // per-block partials of one profile sample
+    int stats_prof_axis;     // axis the two buffers above are sized for (-1: none)
+    double* stats_field;     // 9 N sums
     bool has_ghosts;
 };

@@ -12,19 +12,21 @@ class Solver:
     """One TSLB solver handle (tslb_create) on the current CUDA/HIP device.
 
     State tensors exchanged by ``set_state`` / ``get_state`` are float32 of
-    shape (10, nz, ny, nx): rho - 1, u_x, u_y, u_z, Pi^neq xx, yy, zz, xy, xz, yz.
+    shape (10, nz, ny, nx): rho - 1, u_x, u_y, u_z, Pi^neq xx, yy, zz, xy, xz, yz
+    (with lattice=TSLB_D2Q9, nz = 1 and the z components are zero).
     """
 
     def __init__(self, nx, ny, nz, tau, force=(0.0, 0.0, 0.0), faces=(C.TSLB_PERIODIC,) * 6,
                  storage=C.TSLB_FP32, scale=(0.0, 0.0, 0.0), inlet_u=(0.0, 0.0, 0.0), inlet_center=(0.0, 0.0),
-                 inlet_radius=0.0, inlet_noise=0.0, seed=0, kernel=None, order=3, inlet_noise_kind=0):
+                 inlet_radius=0.0, inlet_noise=0.0, seed=0, kernel=None, order=3, inlet_noise_kind=0,
+                 lattice=C.TSLB_D3Q27):
         self.shape = (nz, ny, nx)
         self.N = nx * ny * nz
         self.device = torch.device("cuda", torch.cuda.current_device())
         bc = C.make_bc(faces=faces, inlet_u=inlet_u, inlet_center=inlet_center, inlet_radius=inlet_radius,
                        inlet_noise=inlet_noise, seed=seed, storage=storage, scale=scale, order=order,
                        inlet_noise_kind=inlet_noise_kind)
-        self.h = C.tslb_create(nx, ny, nz, C.TSLB_D3Q27, tau, force, bc)
+        self.h = C.tslb_create(nx, ny, nz, lattice, tau, force, bc)
         if kernel is not None:
             C.tslb_set_kernel(self.h, kernel)
 
@@ -62,6 +64,39 @@ class Solver:
 
     def step(self, n=1):
         C.tslb_step(self.h, n)
+
+    # ---- velocity statistics (FP64 sums on the device)
+    def stats_begin(self, profile_axis=None, field=False):
+        """Start accumulating: profile sums along `profile_axis` (0 x, 1 y,
+        2 z) and/or per-node sums (field=True)."""
+        kinds = (C.TSLB_STATS_PROFILE if profile_axis is not None else 0) | (C.TSLB_STATS_FIELD if field else 0)
+        self._stats_axis = profile_axis
+        C.tslb_stats_begin(self.h, kinds, profile_axis if profile_axis is not None else 0)
+
+    def stats_sample(self):
+        C.tslb_stats_sample(self.h)
+
+    def stats_profile(self):
+        """(sums (n_axis, 13) float64 tensor on the host, number of samples)."""
+        n_axis = (self.shape[2], self.shape[1], self.shape[0])[self._stats_axis]
+        rows, ns = C.tslb_stats_profile(self.h, n_axis)
+        return torch.tensor(rows, dtype=torch.float64), ns
+
+    def stats_field(self):
+        """Per-node mean velocity (3, nz, ny, nx) and covariances (6, ...)."""
+        mean = torch.empty((3,) + self.shape, dtype=torch.float32, device=self.device)
+        cov = torch.empty((6,) + self.shape, dtype=torch.float32, device=self.device)
+        C.tslb_stats_field(self.h, mean, cov)
+        return mean, cov
+
+    def stats_jet(self, axis, center):
+        """Centreline velocity and half-width of every cross-section along
+        `axis` from the time-averaged field."""
+        n_axis = (self.shape[2], self.shape[1], self.shape[0])[axis]
+        uc = torch.empty(n_axis, dtype=torch.float32, device=self.device)
+        rh = torch.empty(n_axis, dtype=torch.float32, device=self.device)
+        C.tslb_stats_jet(self.h, axis, center, uc, rh)
+        return uc, rh
 
     def set_relaxation_profile(self, tau_z):
         """Relaxation time per z plane (nz values), or None for the uniform tau."""

@@ -26,7 +26,7 @@ def oracle_grid(case):
                             force=[f32(v) for v in case.force], inlet_u=[f32(v) for v in case.inlet_u],
                             inlet_center=[f32(v) for v in case.inlet_center], inlet_radius=f32(case.inlet_radius),
                             inlet_noise=_amp_ratio(case), seed=case.seed, order=case.order,
-                            noise_kind=case.noise_kind, tau_z=_tau_z32(case))
+                            noise_kind=case.noise_kind, tau_z=_tau_z32(case), lattice=case.lattice)
 
 
 def _amp_ratio(case):
@@ -46,7 +46,7 @@ def gpu_solver(case, storage=0, kernel=None, scale=(0.0, 0.0, 0.0)):
     s = Solver(case.nx, case.ny, case.nz, f32(case.tau), force=[f32(v) for v in case.force], faces=case.faces,
                storage=storage, scale=scale, inlet_u=case.inlet_u, inlet_center=case.inlet_center,
                inlet_radius=case.inlet_radius, inlet_noise=case.inlet_noise, seed=case.seed, kernel=kernel,
-               order=case.order, inlet_noise_kind=case.noise_kind)
+               order=case.order, inlet_noise_kind=case.noise_kind, lattice=case.lattice)
     tz = _tau_z32(case)
     if tz is not None:
         s.set_relaxation_profile(tz)

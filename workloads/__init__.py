@@ -38,6 +38,7 @@ class Case:
     order: int = 3  # Hermite order of the rebuilt populations (2: regularised collision)
     noise_kind: int = 0  # inlet perturbation: 0 uniform, 1 Gaussian
     sponge: tuple = ()  # (K, power, width) of an outlet sponge on the +z face, or ()
+    lattice: int = 27  # 27 (D3Q27) or 9 (D2Q9, nz = 1)
     extra: dict = field(default_factory=dict)
 
     @property
@@ -142,6 +143,31 @@ def paper_jet_case(nx=440, ny=440, nz=600, U=0.05, D=20.0, re=7000.0, steps=2000
                 faces=(PERIODIC, PERIODIC, PERIODIC, PERIODIC, INLET, OUTLET),
                 inlet_u=(0.0, 0.0, U), inlet_center=((nx - 1) / 2.0, (ny - 1) / 2.0),
                 inlet_radius=D / 2.0, inlet_noise=noise, seed=seed, steps=steps, noise_kind=1, sponge=sponge)
+
+
+# --------------------------------------------------------------------------
+# Two-dimensional channel for the D2Q9 lattice: 8192 x 4096 nodes (nz = 1),
+# walls at y = 0 and y = ny - 1, x periodic; the laminar parabola of
+# centreline 0.05 plus seeded uniform 5 % perturbations; the body force of
+# that Poiseuille profile.
+def channel2d_case(nx=8192, ny=4096, tau=0.5045, uc=0.05, seed=5678):
+    nu = (tau - 0.5) / 3.0
+    h = (ny - 2) / 2.0
+    g = 2.0 * nu * uc / (h * h)
+    return Case("channel2d_%dx%d" % (nx, ny), nx, ny, 1, tau, faces=(PERIODIC, PERIODIC, WALL, WALL, PERIODIC, PERIODIC),
+                force=(g, 0.0, 0.0), seed=seed, lattice=9, extra={"h": h, "uc": uc})
+
+
+def channel2d_state(case):
+    h, uc = case.extra["h"], case.extra["uc"]
+    y = np.arange(case.ny) - 0.5  # walls half-way between the solid and first fluid layers
+    prof = np.clip(uc * (1.0 - ((y - h) / h) ** 2), 0.0, None)
+    st = rest_state(case.shape)
+    noise = _rng(case.seed).uniform(-1.0, 1.0, size=(case.ny, case.nx))
+    st[1, 0] = prof[:, None] * (1.0 + 0.05 * noise)
+    st[:, 0, 0, :] = rest_state((1,))[:, 0:1]
+    st[:, 0, -1, :] = rest_state((1,))[:, 0:1]
+    return st
 
 
 def tau_profile(case):
