@@ -254,6 +254,7 @@ WORKLOADS = {
     "jet": lambda W: (lambda c: (c, W.jet_state(c)))(W.jet_case()),
     "paper_jet": lambda W: (lambda c: (c, W.jet_state(c)))(W.paper_jet_case()),
     "channel2d": lambda W: (lambda c: (c, W.channel2d_state(c)))(W.channel2d_case()),
+    "channel_d3q19": lambda W: (lambda c: (c, W.channel_state(c)))(W.channel_case(lattice=19)),
     "cube512": lambda W: (lambda c: (c, W.tgv_state(c.nx, 0.01)))(W.tgv_case(n=512)),
     "tgv32": lambda W: (lambda c: (c, W.tgv_state(c.nx, 0.01)))(W.tgv_case()),
 }
@@ -403,7 +404,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": case.name, "nodes": case.nodes, "lattice": "D2Q9" if case.lattice == 9 else "D3Q27",
+        "config": {"workload": case.name, "nodes": case.nodes, "lattice": {9: "D2Q9", 19: "D3Q19"}.get(case.lattice, "D3Q27"),
                    "tau": case.tau,
                    "storage": "fp32", "faces": list(case.faces), "kernel": kname, "stable": rc == 0},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -417,7 +418,8 @@ def main():
         rec["storage_variants"] = measure_storage_variants(200, 10, args.kernel)
         rec["order_variants"] = measure_order_variants(case, _device_state(st64), 200, 10, args.kernel)
         rec["layout_variants"] = measure_layout_variants(case, _device_state(st64), 200, 10)
-        rec["other_workloads"] = measure_workloads(["cube512", "jet", "paper_jet", "channel2d"], 100, 5, args.kernel)
+        rec["other_workloads"] = measure_workloads(["cube512", "jet", "paper_jet", "channel2d", "channel_d3q19"], 100, 5,
+                                                   args.kernel)
         rec["statistics"] = measure_stats_cost(case, _device_state(st64), 50)
         rec["adjoint"] = measure_adjoint(args.kernel)
         if not args.no_cpu:

@@ -42,7 +42,7 @@ extern "C" {
 
 typedef struct tslb_ctx *tslb_handle; /* opaque, owned by the library */
 
-enum { TSLB_D3Q27 = 27, TSLB_D2Q9 = 9 };                    /* lattices (Section 2.1; D2Q9 = 2D counterpart) */
+enum { TSLB_D3Q27 = 27, TSLB_D3Q19 = 19, TSLB_D2Q9 = 9 };   /* lattices (Section 2.1 and 2.2) */
 enum { TSLB_FP32 = 0, TSLB_FP16 = 1, TSLB_BF16 = 2 };       /* moment storage; compute is FP32 */
 enum { TSLB_PERIODIC = 0, TSLB_WALL = 1, TSLB_INLET = 2, TSLB_OUTLET = 3 }; /* face kinds */
 enum { TSLB_DEVICE = 1, TSLB_RHO_DEVIATION = 2 };           /* set/get flags */
@@ -102,7 +102,12 @@ typedef struct {
 } tslb_bc;
 
 /* Create a solver on an nx*ny*nz grid (Section 2.2 update).
- * lattice: TSLB_D3Q27, or TSLB_D2Q9 (the two-dimensional counterpart: the
+ * lattice: TSLB_D3Q27; TSLB_D3Q19 (the 19 rest, face and edge velocities,
+ *   weights 1/3, 1/18, 1/36: the reconstruction keeps the third-order
+ *   Hermite content this lattice supports, i.e. the three pairs
+ *   (xxy, yzz), (xzz, xyy), (yyz, xxz) projected on their sums and
+ *   differences with the lattice's own norms 2 cs^6 and 6 cs^6, and no xyz
+ *   term; tiled kernel only, no adjoint); or TSLB_D2Q9 (the two-dimensional counterpart: the
  *   same reconstruction on the nine-velocity tensor-product lattice; needs
  *   nz = 1, periodic z faces and zero z components of force and inlet
  *   velocity; the state keeps the ten-field layout with u_z and the Pi

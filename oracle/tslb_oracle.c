@@ -43,7 +43,7 @@ typedef struct {
     int opp[NQ];
 } lattice_t;
 
-static lattice_t LAT27, LAT9;
+static lattice_t LAT27, LAT9, LAT19;
 static const int PI_IDX[3][3] = {{0, 3, 4}, {3, 1, 5}, {4, 5, 2}};
 
 static void build_lattice(lattice_t *L, int d)
@@ -67,16 +67,42 @@ static void build_lattice(lattice_t *L, int d)
             if (L->c[a][0] == -L->c[b][0] && L->c[a][1] == -L->c[b][1] && L->c[a][2] == -L->c[b][2]) L->opp[a] = b;
 }
 
+/* D3Q19: the rest, face and edge velocities of D3Q27 (no corners), with
+ * the unique shell weights for sum w = 1, sum w cx^2 = cs2 and
+ * sum w cx^2 cy^2 = cs2^2: 1/3, 1/18, 1/36.                                 */
+static void build_d3q19(lattice_t *L)
+{
+    const double ws[3] = {1.0 / 3.0, 1.0 / 18.0, 1.0 / 36.0};
+    int i = 0;
+    for (int cx = -1; cx <= 1; cx++)
+        for (int cy = -1; cy <= 1; cy++)
+            for (int cz = -1; cz <= 1; cz++) {
+                const int shell = abs(cx) + abs(cy) + abs(cz);
+                if (shell == 3) continue;
+                L->c[i][0] = cx;
+                L->c[i][1] = cy;
+                L->c[i][2] = cz;
+                L->w[i] = ws[shell];
+                i++;
+            }
+    L->q = i;
+    L->d = 3;
+    for (int a = 0; a < L->q; a++)
+        for (int b = 0; b < L->q; b++)
+            if (L->c[a][0] == -L->c[b][0] && L->c[a][1] == -L->c[b][1] && L->c[a][2] == -L->c[b][2]) L->opp[a] = b;
+}
+
 static void lattice_init(void)
 {
     static int done = 0;
     if (done) return;
     build_lattice(&LAT27, 3);
     build_lattice(&LAT9, 2);
+    build_d3q19(&LAT19);
     done = 1;
 }
 
-static const lattice_t *lattice_of(int id) { return id == 9 ? &LAT9 : &LAT27; }
+static const lattice_t *lattice_of(int id) { return id == 9 ? &LAT9 : (id == 19 ? &LAT19 : &LAT27); }
 
 static double hermite1(const lattice_t *L, int i, int a) { return (double)L->c[i][a]; }
 
@@ -109,7 +135,7 @@ typedef struct {
     int order; /* Hermite order of the reconstruction: 3 (Section 2.2) or 2 (Eq. (fullstrcoll)) */
     int noise_kind; /* inlet perturbation: 0 uniform in [-1, 1), 1 standard Gaussian (Section 3.2) */
     const double *tau_z; /* relaxation time of each z plane (the jet's outlet sponge), or NULL: tau */
-    int lattice; /* 27 (or 0): D3Q27; 9: D2Q9 on an nz = 1 grid with periodic z faces */
+    int lattice; /* 27 (or 0): D3Q27; 19: D3Q19; 9: D2Q9 on an nz = 1 grid with periodic z faces */
 } or_grid;
 
 static const lattice_t *lat(const or_grid *G) { return lattice_of(G->lattice); }
@@ -445,6 +471,7 @@ double or_inlet_gauss(uint64_t seed, long t, long n, long N, int a) { return inl
 int or_jvp_step(const or_grid *G, const double *st, const double *gf, const double *dst, const double *dgf,
                 long t, double *dout)
 {
+    if (G->lattice != 0 && G->lattice != 27) return -3; /* derivatives: D3Q27 only */
     lattice_init();
     const long N = (long)G->nx * G->ny * G->nz;
     double complex *a = (double complex *)malloc(sizeof(double complex) * 10 * N);
@@ -553,6 +580,7 @@ static int adjoint_node(const or_grid *G, const double *st, const double *gf, co
 int or_adjoint_step(const or_grid *G, const double *st, const double *gf, const double *lam1, double *lam0,
                     double *dg)
 {
+    if (G->lattice != 0 && G->lattice != 27) return -3; /* derivatives: D3Q27 only */
     lattice_init();
     if (grid_has_ghosts(G)) return -1;
     const long N = (long)G->nx * G->ny * G->nz;
@@ -577,6 +605,7 @@ int or_adjoint_step(const or_grid *G, const double *st, const double *gf, const 
 int or_adjoint_nodes(const or_grid *G, const double *st, const double *gf, const double *lam1, const long *idx,
                      long nidx, double *lam_out, double *dg_out)
 {
+    if (G->lattice != 0 && G->lattice != 27) return -3; /* derivatives: D3Q27 only */
     lattice_init();
     if (grid_has_ghosts(G)) return -1;
 #pragma omp parallel for schedule(dynamic, 4)
@@ -613,6 +642,7 @@ double or_ke_seed(const or_grid *G, const double *st, double *lam)
 int or_rollout_grad(const or_grid *G, const double *st0, const double *gf, long t0, int nsteps, double *loss,
                     double *lam0, double *dg)
 {
+    if (G->lattice != 0 && G->lattice != 27) return -3; /* derivatives: D3Q27 only */
     lattice_init();
     if (grid_has_ghosts(G)) return -1;
     const long N = (long)G->nx * G->ny * G->nz;

@@ -12,7 +12,7 @@ import os
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libtslb.so")
 
-TSLB_D3Q27, TSLB_D2Q9 = 27, 9
+TSLB_D3Q27, TSLB_D3Q19, TSLB_D2Q9 = 27, 19, 9
 TSLB_FP32, TSLB_FP16, TSLB_BF16 = 0, 1, 2
 TSLB_PERIODIC, TSLB_WALL, TSLB_INLET, TSLB_OUTLET = 0, 1, 2, 3
 TSLB_DEVICE, TSLB_RHO_DEVIATION = 1, 2

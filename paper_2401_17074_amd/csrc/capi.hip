@@ -51,7 +51,7 @@ hipError_t run_main_update(tslb_ctx* h, const void* in, void* out, hipStream_t s
 
 hipError_t run_update(tslb_ctx* h, const void* in, void* out, hipStream_t s) {
     hipError_t e = run_main_update(h, in, out, s);
-    if (e != hipSuccess || h->kernel != 0 || h->lattice != TSLB_D3Q27) return e;
+    if (e != hipSuccess || h->kernel != 0 || h->lattice == TSLB_D2Q9) return e;
     return launch_wall_fixup(h->storage, in, out, h->p, s);
 }
 
@@ -90,8 +90,8 @@ int tslb_create(int nx, int ny, int nz, int lattice, float tau, const float forc
                 tslb_handle* out) {
     if (!out) return fail(TSLB_E_INVALID, "out handle pointer is NULL");
     *out = nullptr;
-    if (lattice != TSLB_D3Q27 && lattice != TSLB_D2Q9)
-        return fail(TSLB_E_UNSUPPORTED, "lattice %d: D3Q27 (27) and D2Q9 (9) are provided", lattice);
+    if (lattice != TSLB_D3Q27 && lattice != TSLB_D3Q19 && lattice != TSLB_D2Q9)
+        return fail(TSLB_E_UNSUPPORTED, "lattice %d: D3Q27 (27), D3Q19 (19) and D2Q9 (9) are provided", lattice);
     if (nx < 1 || ny < 1 || nz < 1) return fail(TSLB_E_INVALID, "grid dimensions must be >= 1");
     if (!(tau > 0.5f) || !isfinite(tau)) return fail(TSLB_E_INVALID, "tau must exceed 1/2 (got %g)", (double)tau);
     tslb_bc b;
@@ -147,6 +147,7 @@ int tslb_create(int nx, int ny, int nz, int lattice, float tau, const float forc
     h->p.one_minus_omega = (float)(1.0 - 1.0 / (double)tau);
     h->p.order = b.order;
     h->p.dims = lattice == TSLB_D2Q9 ? 2 : 3;
+    h->p.lattice = lattice;
     h->lattice = lattice;
     h->stats_prof_axis = -1;
     for (int a = 0; a < 3; ++a) h->p.force[a] = force ? force[a] : 0.0f;
@@ -222,7 +223,7 @@ int tslb_set_kernel(tslb_handle h, int variant) {
     if (!h) return fail(TSLB_E_INVALID, "NULL handle");
     if (variant < 0 || variant > 2) return fail(TSLB_E_INVALID, "kernel variant %d out of range", variant);
     if (h->lattice != TSLB_D3Q27 && variant != 0)
-        return fail(TSLB_E_UNSUPPORTED, "D2Q9 has one update kernel (variant 0)");
+        return fail(TSLB_E_UNSUPPORTED, "D3Q19 and D2Q9 have one update kernel (variant 0)");
     if (variant == 2 && !h->pop) {
         DeviceGuard dg(h->device);
         const size_t bytes = sizeof(float) * 27 * (size_t)h->p.geo.N;
@@ -453,7 +454,7 @@ int tslb_step_timed(tslb_handle h, int nsteps, double ms[2], void* stream) {
         hipError_t e = hipEventRecord(ev[3 * k], s);
         if (e == hipSuccess) e = run_main_update(h, in, out, s);
         if (e == hipSuccess) e = hipEventRecord(ev[3 * k + 1], s);
-        if (e == hipSuccess && h->kernel == 0 && h->lattice == TSLB_D3Q27)
+        if (e == hipSuccess && h->kernel == 0 && h->lattice != TSLB_D2Q9)
             e = launch_wall_fixup(h->storage, in, out, h->p, s);
         if (e != hipSuccess) {
             rc = fail(TSLB_E_HIP, "timed step: %s", hipGetErrorString(e));

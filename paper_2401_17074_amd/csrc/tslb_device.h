@@ -209,23 +209,28 @@ struct MomentSums {
 // sum f = 1 + D/216, sum f c = J/216 and sum f c c = delta/3 + S/216:
 //   drho' = D/216,  u' = J / (216 + D),
 //   Pi'   = (S - J u' - D/3 delta) / 216.
+// SCALE is the exact factor the populations carry: 216 for the D3Q27
+// weights (216 w = 4^n0), 36 for D3Q19 (36 w = 12, 2, 1 for the rest, face
+// and edge velocities).
+template <int SCALE = 216>
 __device__ __forceinline__ void finalize(const MomentSums& a, float out[10]) {
-    // 1 / (216 + D): hardware reciprocal refined by one Newton step
-    const float den = 216.0f + a.d;
+    constexpr float kInv = 1.0f / (float)SCALE;
+    // 1 / (SCALE + D): hardware reciprocal refined by one Newton step
+    const float den = (float)SCALE + a.d;
     float inv = __builtin_amdgcn_rcpf(den);
     inv = inv * fmaf(-den, inv, 2.0f);
     const float ux = a.j[0] * inv, uy = a.j[1] * inv, uz = a.j[2] * inv;
     const float d3 = a.d * (1.0f / 3.0f);
-    out[0] = a.d * kInv216;
+    out[0] = a.d * kInv;
     out[1] = ux;
     out[2] = uy;
     out[3] = uz;
-    out[4] = (a.s[0] - a.j[0] * ux - d3) * kInv216;
-    out[5] = (a.s[1] - a.j[1] * uy - d3) * kInv216;
-    out[6] = (a.s[2] - a.j[2] * uz - d3) * kInv216;
-    out[7] = (a.s[3] - a.j[0] * uy) * kInv216;
-    out[8] = (a.s[4] - a.j[0] * uz) * kInv216;
-    out[9] = (a.s[5] - a.j[1] * uz) * kInv216;
+    out[4] = (a.s[0] - a.j[0] * ux - d3) * kInv;
+    out[5] = (a.s[1] - a.j[1] * uy - d3) * kInv;
+    out[6] = (a.s[2] - a.j[2] * uz - d3) * kInv;
+    out[7] = (a.s[3] - a.j[0] * uy) * kInv;
+    out[8] = (a.s[4] - a.j[0] * uz) * kInv;
+    out[9] = (a.s[5] - a.j[1] * uz) * kInv;
 }
 
 // Compile-time loop over the 27 velocities.

@@ -14,7 +14,8 @@ struct StepParams {
     Geometry geo;
     float one_minus_omega;   // 1 - 1/tau
     int order;               // Hermite order of the rebuilt populations (2 or 3)
-    int dims;                // 3 (D3Q27) or 2 (D2Q9: u_z and the z components of Pi stay zero)
+    int dims;                // 3 (D3Q27, D3Q19) or 2 (D2Q9: u_z and the z components of Pi stay zero)
+    int lattice;             // 27, 19 or 9
     const float* omo_z;      // optional 1 - omega per z plane (nz floats), else one_minus_omega
     float force[3];          // uniform acceleration (used when gfield == nullptr)
     const float* gfield;     // optional per-node acceleration, 3N SoA

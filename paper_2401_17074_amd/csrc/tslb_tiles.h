@@ -58,7 +58,14 @@ enum {
 // (1 - omega) [9/2 cPc - 3/2 tr Pi + 27/2 cPc cu - 9/2 tr Pi cu - 9 c.Pi u].
 // ORDER 2 keeps the terms up to H2 only (Eq. (fullstrcoll)): the cubic
 // monomials vanish and the linear ones reduce to 3 rho (u + g).
-template <int ORDER = 3>
+// LAT 19 (D3Q19) keeps the third-order content that lattice supports: with
+// a3 = rho u u u + sym((1 - omega) Pi u), each pair (a_xxy, a_yzz),
+// (a_xzz, a_xyy), (a_yyz, a_xxz) enters as h+ A+ / (2 cs6) + h- A- / (6 cs6)
+// (A+- = sum / difference of the pair, h+- the matching Hermite
+// combinations, whose norms on D3Q19 are 2 cs6 and 6 cs6), and there is no
+// c_x c_y c_z term.  Expanded in monomials: the pair (xxy, yzz) gives
+// c_x^2 c_y (27/2 A+ + 9/2 A-), c_y c_z^2 (27/2 A+ - 9/2 A-) and -9 A+ c_y.
+template <int ORDER = 3, int LAT = 27>
 __host__ __device__ inline void coefficients(const float m[10], const float g[3], float omo, float A[NK]) {
     const float dr = m[0], rho = 1.0f + dr;
     const float ux = m[1], uy = m[2], uz = m[3];
@@ -82,6 +89,28 @@ __host__ __device__ inline void coefficients(const float m[10], const float g[3]
         A[K210] = A[K201] = A[K120] = A[K021] = A[K102] = A[K012] = A[K111] = 0.0f;
         return;
     }
+    if constexpr (LAT == 19) {
+        const float axxy = rx * ux * uy + pxx * uy + 2.0f * pxy * ux;
+        const float ayzz = ry * uz * uz + pzz * uy + 2.0f * pyz * uz;
+        const float axzz = rx * uz * uz + pzz * ux + 2.0f * pxz * uz;
+        const float axyy = rx * uy * uy + pyy * ux + 2.0f * pxy * uy;
+        const float ayyz = ry * uy * uz + pyy * uz + 2.0f * pyz * uy;
+        const float axxz = rx * ux * uz + pxx * uz + 2.0f * pxz * ux;
+        const float ap = axxy + ayzz, am = axxy - ayzz;
+        const float bp = axzz + axyy, bm = axzz - axyy;
+        const float cp = ayyz + axxz, cm = ayyz - axxz;
+        A[K210] = 13.5f * ap + 4.5f * am;
+        A[K012] = 13.5f * ap - 4.5f * am;
+        A[K102] = 13.5f * bp + 4.5f * bm;
+        A[K120] = 13.5f * bp - 4.5f * bm;
+        A[K021] = 13.5f * cp + 4.5f * cm;
+        A[K201] = 13.5f * cp - 4.5f * cm;
+        A[K111] = 0.0f;
+        A[K100] = 3.0f * (rx + rho * g[0]) - 9.0f * bp;
+        A[K010] = 3.0f * (ry + rho * g[1]) - 9.0f * ap;
+        A[K001] = 3.0f * (rz + rho * g[2]) - 9.0f * cp;
+        return;
+    }
     const float base = 3.0f - 4.5f * u2;
     const float pux = pxx * ux + pxy * uy + pxz * uz;
     const float puy = pxy * ux + pyy * uy + pyz * uz;
@@ -99,10 +128,18 @@ __host__ __device__ inline void coefficients(const float m[10], const float g[3]
     A[K111] = 27.0f * (rx * uy * uz + pxy * uz + pxz * uy + pyz * ux);
 }
 
+// Exact scaled weight of a velocity with n0 zero components: 216 w = 4^n0
+// on D3Q27; 36 w = 0, 1, 2, 12 on D3Q19 (corners carry no population).
+template <int LAT>
+__host__ __device__ constexpr float scaled_weight(int n0) {
+    if constexpr (LAT == 19) return n0 == 3 ? 12.0f : (n0 == 2 ? 2.0f : (n0 == 1 ? 1.0f : 0.0f));
+    return (float)(1 << (2 * n0));
+}
+
 // Values of the 2D polynomial Q(cx, cy) = sum b_ab cx^a cy^b on the 3 x 3
 // velocity grid of one cz slice, written to G[base + 3 (cy + 1) + (cx + 1)]
-// with the exact weight factor 4^n0 applied.
-template <int CZ>
+// with the exact scaled weight applied.
+template <int CZ, int LAT = 27>
 __device__ __forceinline__ void eval_slice(float b00, float b10, float b01, float b20, float b02, float b11, float b21,
                                            float b12, float G[27]) {
     // along x for each power of cy
@@ -117,19 +154,20 @@ __device__ __forceinline__ void eval_slice(float b00, float b10, float b01, floa
 #pragma unroll
         for (int iy = 0; iy < 3; ++iy) {
             const int I = 9 * (CZ + 1) + 3 * iy + ix;
-            const float w = (float)(1 << (2 * ((ix == 1) + (iy == 1) + (CZ == 0))));
-            G[I] = (w == 1.0f) ? q[iy] : w * q[iy];
+            const float w = scaled_weight<LAT>((ix == 1) + (iy == 1) + (CZ == 0));
+            G[I] = (w == 0.0f) ? 0.0f : ((w == 1.0f) ? q[iy] : w * q[iy]);
         }
     }
 }
 
+template <int LAT = 27>
 __device__ __forceinline__ void populations(const float A[NK], float G[27]) {
-    eval_slice<0>(A[K000], A[K100], A[K010], A[K200], A[K020], A[K110], A[K210], A[K120], G);
+    eval_slice<0, LAT>(A[K000], A[K100], A[K010], A[K200], A[K020], A[K110], A[K210], A[K120], G);
     const float e00 = A[K000] + A[K002], e10 = A[K100] + A[K102], e01 = A[K010] + A[K012];
-    eval_slice<1>(e00 + A[K001], e10 + A[K101], e01 + A[K011], A[K200] + A[K201], A[K020] + A[K021],
-                  A[K110] + A[K111], A[K210], A[K120], G);
-    eval_slice<-1>(e00 - A[K001], e10 - A[K101], e01 - A[K011], A[K200] - A[K201], A[K020] - A[K021],
-                   A[K110] - A[K111], A[K210], A[K120], G);
+    eval_slice<1, LAT>(e00 + A[K001], e10 + A[K101], e01 + A[K011], A[K200] + A[K201], A[K020] + A[K021],
+                       A[K110] + A[K111], A[K210], A[K120], G);
+    eval_slice<-1, LAT>(e00 - A[K001], e10 - A[K101], e01 - A[K011], A[K200] - A[K201], A[K020] - A[K021],
+                        A[K110] - A[K111], A[K210], A[K120], G);
 }
 
 // Moments of one arriving cz slice F[cy+1][cx+1], added to the output plane

@@ -129,15 +129,11 @@ __global__ void __launch_bounds__(kD2Block) update_d2q9_kernel(const typename S:
     const bool col_solid = (x == 0 && (g.lo_solid & 1)) || (x == nx - 1 && (g.hi_solid & 1));
     const float omo = omo_at(p, 0);
 
-    // moments of the row being processed; the next row's loads are issued
-    // into the same registers as soon as this row's terms are formed, so
-    // they are in flight during the exchange, the reduction and the stores
-    float m[6];
-    load6<S>(in, N, x + (long long)nx * wrap_clamp(y0 - 1, ny, py), p, m);
-
     auto row = [&](int yp, Sums2& aprev, Sums2& acur, Sums2& anext) {
         const int y = wrap_clamp(yp, ny, py);
         const long long n = x + (long long)nx * y;
+        float m[6];
+        load6<S>(in, N, n, p, m);
         const bool solid = col_solid || (y == 0 && (g.lo_solid & 2)) || (y == ny - 1 && (g.hi_solid & 2));
         float gxv = 0.0f, gyv = 0.0f;
         if (!solid) {
@@ -145,7 +141,6 @@ __global__ void __launch_bounds__(kD2Block) update_d2q9_kernel(const typename S:
             gyv = FIELD ? p.gfield[N + n] : p.force[1];
         }
         const Terms2 t = terms2(m, gxv, gyv, omo);
-        if (yp + 1 <= y1) load6<S>(in, N, x + (long long)nx * wrap_clamp(yp + 1, ny, py), p, m);
         float G[9];
         G[0] = emit9<0, ORDER>(t);
         G[1] = emit9<1, ORDER>(t);

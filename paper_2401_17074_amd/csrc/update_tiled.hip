@@ -31,7 +31,7 @@ namespace {
 using namespace tile;
 
 
-template <class S, bool WALLS, bool FIELD, int ORDER>
+template <class S, bool WALLS, bool FIELD, int ORDER, int LAT>
 __global__ void __launch_bounds__(NTHREADS, TSLB_WAVES_PER_EU) update_tiled_kernel(const FieldPtrs<typename S::T> f, StepParams p,
                                                                    int tiles_x, int tiles_y, int tiles_z, int TZ) {
     __shared__ float lds_all[NBUF][NSLOT][LY][LX];
@@ -145,11 +145,11 @@ __global__ void __launch_bounds__(NTHREADS, TSLB_WAVES_PER_EU) update_tiled_kern
                 const bool plane_solid = (zlo_wall && zp == 0) || (zhi_wall && zp == nz - 1);
                 const float gp = plane_solid ? 0.0f : 1.0f;
                 const float gz[3] = {gp * gacc[0], gp * gacc[1], gp * gacc[2]};
-                coefficients<ORDER>(mcur, gz, omo, A);
+                coefficients<ORDER, LAT>(mcur, gz, omo, A);
             } else {
-                coefficients<ORDER>(mcur, gacc, omo, A);
+                coefficients<ORDER, LAT>(mcur, gacc, omo, A);
             }
-            populations(A, G);
+            populations<LAT>(A, G);
             Unroll<0, 27>::run([&]<int I>() {
                 if constexpr (cx_of(I) != 0 || cy_of(I) != 0) lds[slot_of(I)][ly][lx] = G[I];
             });
@@ -201,7 +201,7 @@ __global__ void __launch_bounds__(NTHREADS, TSLB_WAVES_PER_EU) update_tiled_kern
                 for (int k = 0; k < 6; ++k) side[4 + k] = aprev.s[k];
             } else if (fl) {
                 float m[10];
-                finalize(aprev, m);
+                finalize<LAT == 19 ? 36 : 216>(aprev, m);
                 const unsigned on = (col + plane_nodes * (unsigned)zo) * (unsigned)sizeof(typename S::T);
                 store_out(at(f.out[0], on), S::store(m[0], p.scale[0]));
 #pragma unroll
@@ -243,7 +243,7 @@ __global__ void __launch_bounds__(NTHREADS, TSLB_WAVES_PER_EU) update_tiled_kern
 // the raw sums the update left in the side buffer, then finalises and
 // stores.  Threads enumerate the layers next to each wall face; a node next
 // to several walls is done once, by its first wall face.
-template <class S, int ORDER>
+template <class S, int ORDER, int LAT>
 __global__ void __launch_bounds__(256) wall_fixup_kernel(const FieldPtrs<typename S::T> f, StepParams p,
                                                          long long total) {
     const Geometry& g = p.geo;
@@ -273,8 +273,8 @@ __global__ void __launch_bounds__(256) wall_fixup_kernel(const FieldPtrs<typenam
 #pragma unroll
     for (int a = 0; a < 3; ++a) gg[a] = f.g[a] ? ld_at(f.g[a], node * 4u) : p.force[a];
     float A[NK], G[27];
-    coefficients<ORDER>(m, gg, omo_at(p, c[2]), A);
-    populations(A, G);
+    coefficients<ORDER, LAT>(m, gg, omo_at(p, c[2]), A);
+    populations<LAT>(A, G);
 
     const float* side = p.wall_side + 10 * local + 10 * p.wall_off[fw];
     MomentSums a;
@@ -289,7 +289,7 @@ __global__ void __launch_bounds__(256) wall_fixup_kernel(const FieldPtrs<typenam
         if (upstream_solid<I>(wf, zlo, zhi)) a.template add<I>(G[26 - I]);
     });
     float out[10];
-    finalize(a, out);
+    finalize<LAT == 19 ? 36 : 216>(a, out);
     const unsigned on = node * (unsigned)sizeof(typename S::T);
     *at(f.out[0], on) = S::store(out[0], p.scale[0]);
 #pragma unroll
@@ -298,7 +298,7 @@ __global__ void __launch_bounds__(256) wall_fixup_kernel(const FieldPtrs<typenam
     for (int q = 4; q < 10; ++q) *at(f.out[q], on) = S::store(out[q], p.scale[2]);
 }
 
-template <class S, bool WALLS, bool FIELD, int ORDER>
+template <class S, bool WALLS, bool FIELD, int ORDER, int LAT>
 hipError_t launch_t(const void* in, void* out, const StepParams& p, hipStream_t s) {
     const int tiles_x = (p.geo.n[0] + TX - 1) / TX;
     const int tiles_y = (p.geo.n[1] + TY - 1) / TY;
@@ -307,23 +307,30 @@ hipError_t launch_t(const void* in, void* out, const StepParams& p, hipStream_t 
     const unsigned nblk = (unsigned)tiles_x * tiles_y * tiles_z;
     if (p.geo.N >= (1LL << 30)) return hipErrorInvalidValue;  // 32-bit node offsets
     const FieldPtrs<typename S::T> f = field_ptrs<S>(in, out, p);
-    hipLaunchKernelGGL((update_tiled_kernel<S, WALLS, FIELD, ORDER>), dim3(nblk), dim3(NTHREADS), 0, s, f, p, tiles_x,
+    hipLaunchKernelGGL((update_tiled_kernel<S, WALLS, FIELD, ORDER, LAT>), dim3(nblk), dim3(NTHREADS), 0, s, f, p, tiles_x,
                        tiles_y, tiles_z, TZ);
     return hipGetLastError();
 }
 
-template <class S, int ORDER>
+template <class S, int ORDER, int LAT>
 hipError_t launch_o(const void* in, void* out, const StepParams& p, hipStream_t s) {
     const bool walls = (p.geo.lo_solid | p.geo.hi_solid) != 0;
     const bool field = p.gfield != nullptr;
     if (walls)
-        return field ? launch_t<S, true, true, ORDER>(in, out, p, s) : launch_t<S, true, false, ORDER>(in, out, p, s);
-    return field ? launch_t<S, false, true, ORDER>(in, out, p, s) : launch_t<S, false, false, ORDER>(in, out, p, s);
+        return field ? launch_t<S, true, true, ORDER, LAT>(in, out, p, s)
+                     : launch_t<S, true, false, ORDER, LAT>(in, out, p, s);
+    return field ? launch_t<S, false, true, ORDER, LAT>(in, out, p, s)
+                 : launch_t<S, false, false, ORDER, LAT>(in, out, p, s);
+}
+
+template <class S, int LAT>
+hipError_t launch_l(const void* in, void* out, const StepParams& p, hipStream_t s) {
+    return p.order == 2 ? launch_o<S, 2, LAT>(in, out, p, s) : launch_o<S, 3, LAT>(in, out, p, s);
 }
 
 template <class S>
 hipError_t launch_s(const void* in, void* out, const StepParams& p, hipStream_t s) {
-    return p.order == 2 ? launch_o<S, 2>(in, out, p, s) : launch_o<S, 3>(in, out, p, s);
+    return p.lattice == 19 ? launch_l<S, 19>(in, out, p, s) : launch_l<S, 27>(in, out, p, s);
 }
 
 }  // namespace
@@ -334,10 +341,16 @@ hipError_t fixup_s(const void* in, void* out, const StepParams& p, hipStream_t s
     const FieldPtrs<typename S::T> f = field_ptrs<S>(in, out, p);
     const int block = 256;
     const unsigned grid = (unsigned)((p.wall_nodes + block - 1) / block);
-    if (p.order == 2)
-        hipLaunchKernelGGL((wall_fixup_kernel<S, 2>), dim3(grid), dim3(block), 0, s, f, p, p.wall_nodes);
-    else
-        hipLaunchKernelGGL((wall_fixup_kernel<S, 3>), dim3(grid), dim3(block), 0, s, f, p, p.wall_nodes);
+    if (p.lattice == 19) {
+        if (p.order == 2)
+            hipLaunchKernelGGL((wall_fixup_kernel<S, 2, 19>), dim3(grid), dim3(block), 0, s, f, p, p.wall_nodes);
+        else
+            hipLaunchKernelGGL((wall_fixup_kernel<S, 3, 19>), dim3(grid), dim3(block), 0, s, f, p, p.wall_nodes);
+    } else if (p.order == 2) {
+        hipLaunchKernelGGL((wall_fixup_kernel<S, 2, 27>), dim3(grid), dim3(block), 0, s, f, p, p.wall_nodes);
+    } else {
+        hipLaunchKernelGGL((wall_fixup_kernel<S, 3, 27>), dim3(grid), dim3(block), 0, s, f, p, p.wall_nodes);
+    }
     return hipGetLastError();
 }
 

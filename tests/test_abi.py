@@ -46,7 +46,8 @@ def test_struct_layout_matches_header():
 
 
 @pytest.mark.parametrize("args,code", [
-    ((8, 8, 8, 19, 0.8), -2),     # only D3Q27
+    ((8, 8, 8, 15, 0.8), -2),     # D3Q27, D3Q19 and D2Q9 only
+    ((8, 8, 2, 9, 0.8), -1),      # D2Q9 needs nz = 1
     ((8, 8, 8, 27, 0.5), -1),     # tau must exceed 1/2
     ((0, 8, 8, 27, 0.8), -1),     # dims
     ((8, 8, 8, 27, float("nan")), -1),

@@ -82,16 +82,17 @@ def tgv_state(n=32, u0=0.01):
 # Channel: walls are the node layers y = 0 and y = ny - 1 (solid), x and z
 # periodic.  Friction Reynolds number 180 with tau = 0.5045 (nu = 0.0015):
 # half-width h = (ny - 2) / 2, u_tau = Re_tau nu / h, g = u_tau^2 / h along x.
-def channel_case(nx=384, ny=192, nz=192, re_tau=180.0, tau=0.5045, steps=1000, seed=1234, uc=None):
+def channel_case(nx=384, ny=192, nz=192, re_tau=180.0, tau=0.5045, steps=1000, seed=1234, uc=None, lattice=27):
     nu = (tau - 0.5) / 3.0
     h = (ny - 2) / 2.0
     u_tau = re_tau * nu / h
     g = u_tau * u_tau / h
     if uc is None:
         uc = 20.0 * u_tau  # centreline of the initial parabola: a low-Mach stand-in
-    return Case("channel_%dx%dx%d" % (nx, ny, nz), nx, ny, nz, tau,
+    name = "channel_%dx%dx%d" % (nx, ny, nz) + ("" if lattice == 27 else "_d3q%d" % lattice)
+    return Case(name, nx, ny, nz, tau,
                 faces=(PERIODIC, PERIODIC, WALL, WALL, PERIODIC, PERIODIC),
-                force=(g, 0.0, 0.0), seed=seed, steps=steps,
+                force=(g, 0.0, 0.0), seed=seed, steps=steps, lattice=lattice,
                 extra={"u_tau": u_tau, "h": h, "uc": uc, "perturb": 0.05})
 
 
