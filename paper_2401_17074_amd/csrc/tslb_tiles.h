@@ -30,12 +30,20 @@ namespace tile {
 #ifndef TSLB_PREFETCH_DEPTH
 #define TSLB_PREFETCH_DEPTH 1
 #endif
+// 1 (default): the tiled update adds the bounced-back populations of
+// wall-adjacent nodes itself, from the populations the node has just built;
+// 0: it leaves their raw sums in a side buffer for the wall fix-up launch
+#ifndef TSLB_FUSED_WALLS
+#define TSLB_FUSED_WALLS 1
+#endif
 constexpr int TX = TSLB_TILE_X;              // interior tile width (64: one wave per row)
 constexpr int TY = TSLB_TILE_Y;              // interior rows
 constexpr int LX = TX + 2, LY = TY + 2;      // LDS tile with halo
 constexpr int NINT = TX * TY;                // interior threads (whole waves)
 constexpr int NHALO = 2 * LX + 2 * TY;       // halo columns
 constexpr int NTHREADS = NINT + ((NHALO + 63) / 64) * 64;
+static_assert(NINT % 64 == 0, "interior threads must fill whole wavefronts");
+static_assert(NTHREADS <= 1024, "a block holds at most 1024 threads");
 constexpr int NSLOT = 24;                    // populations with (cx, cy) != (0, 0)
 // With two LDS buffers (alternating planes) one barrier per plane suffices:
 // a thread writes plane p + 1 only after it has gathered plane p, and the
@@ -111,21 +119,24 @@ __host__ __device__ inline void coefficients(const float m[10], const float g[3]
         A[K001] = 3.0f * (rz + rho * g[2]) - 9.0f * cp;
         return;
     }
+    // The same expansion, arranged to reuse the quadratic coefficients:
+    // 27/2 (rho u_a^2 u_b + Pi_aa u_b + 2 Pi_ab u_a) = 3 K_aa u_b + 27 Pi_ab u_a,
+    // and in the linear ones the Pi_aa u_a terms of 4.5 rho u_a^3 +
+    // 27/2 Pi_aa u_a - 9 (Pi u)_a collapse into K_aa u_a.
     const float base = 3.0f - 4.5f * u2;
-    const float pux = pxx * ux + pxy * uy + pxz * uz;
-    const float puy = pxy * ux + pyy * uy + pyz * uz;
-    const float puz = pxz * ux + pyz * uy + pzz * uz;
     const float t45 = 4.5f * tr;
-    A[K100] = rx * (base + 4.5f * uxx) + ux * (13.5f * pxx - t45) - 9.0f * pux + 3.0f * rho * g[0];
-    A[K010] = ry * (base + 4.5f * uyy) + uy * (13.5f * pyy - t45) - 9.0f * puy + 3.0f * rho * g[1];
-    A[K001] = rz * (base + 4.5f * uzz) + uz * (13.5f * pzz - t45) - 9.0f * puz + 3.0f * rho * g[2];
-    A[K210] = 13.5f * (rx * ux * uy + pxx * uy + 2.0f * pxy * ux);
-    A[K201] = 13.5f * (rx * ux * uz + pxx * uz + 2.0f * pxz * ux);
-    A[K120] = 13.5f * (ry * uy * ux + pyy * ux + 2.0f * pxy * uy);
-    A[K021] = 13.5f * (ry * uy * uz + pyy * uz + 2.0f * pyz * uy);
-    A[K102] = 13.5f * (rz * uz * ux + pzz * ux + 2.0f * pxz * uz);
-    A[K012] = 13.5f * (rz * uz * uy + pzz * uy + 2.0f * pyz * uz);
-    A[K111] = 27.0f * (rx * uy * uz + pxy * uz + pxz * uy + pyz * ux);
+    A[K100] = rx * base + ux * (A[K200] - t45) - 9.0f * (pxy * uy + pxz * uz) + 3.0f * rho * g[0];
+    A[K010] = ry * base + uy * (A[K020] - t45) - 9.0f * (pxy * ux + pyz * uz) + 3.0f * rho * g[1];
+    A[K001] = rz * base + uz * (A[K002] - t45) - 9.0f * (pxz * ux + pyz * uy) + 3.0f * rho * g[2];
+    const float qxy = 27.0f * pxy, qxz = 27.0f * pxz, qyz = 27.0f * pyz;
+    const float sxx = 3.0f * A[K200], syy = 3.0f * A[K020], szz = 3.0f * A[K002];
+    A[K210] = sxx * uy + qxy * ux;
+    A[K201] = sxx * uz + qxz * ux;
+    A[K120] = syy * ux + qxy * uy;
+    A[K021] = syy * uz + qyz * uy;
+    A[K102] = szz * ux + qxz * uz;
+    A[K012] = szz * uy + qyz * uz;
+    A[K111] = 3.0f * A[K110] * uz + qxz * uy + qyz * ux;
 }
 
 // Exact scaled weight of a velocity with n0 zero components: 216 w = 4^n0

@@ -150,6 +150,17 @@ __global__ void __launch_bounds__(NTHREADS, TSLB_WAVES_PER_EU) update_tiled_kern
                 coefficients<ORDER, LAT>(mcur, gacc, omo, A);
             }
             populations<LAT>(A, G);
+            if (WALLS && TSLB_FUSED_WALLS && interior && col_fluid) {
+                // half-way bounce-back in place: a fluid node next to a wall
+                // receives its own population along -c for every c whose
+                // upstream node is solid; it holds those values right here
+                const bool zlo_adj = zlo_wall && zp == 1, zhi_adj = zhi_wall && zp == nz - 2;
+                if (wf != 0 || zlo_adj || zhi_adj) {
+                    Unroll<0, 27>::run([&]<int I>() {
+                        if (upstream_solid<I>(wf, zlo_adj, zhi_adj)) acur.template add<I>(G[26 - I]);
+                    });
+                }
+            }
             Unroll<0, 27>::run([&]<int I>() {
                 if constexpr (cx_of(I) != 0 || cy_of(I) != 0) lds[slot_of(I)][ly][lx] = G[I];
             });
@@ -187,7 +198,8 @@ __global__ void __launch_bounds__(NTHREADS, TSLB_WAVES_PER_EU) update_tiled_kern
         const int zo = zp - 1;
         if (interior && zo >= zs && zo < ze) {
             const bool fl = col_fluid && !(zo == 0 && zlo_out) && !(zo == nz - 1 && zhi_out);
-            const bool near_wall = WALLS && (wf != 0 || (zlo_wall && zo == 1) || (zhi_wall && zo == nz - 2));
+            const bool near_wall =
+                WALLS && !TSLB_FUSED_WALLS && (wf != 0 || (zlo_wall && zo == 1) || (zhi_wall && zo == nz - 2));
             if (fl && near_wall) {
                 // next to a wall: the bounced-back populations are still missing;
                 // leave the raw sums for the fix-up pass
@@ -337,7 +349,7 @@ hipError_t launch_s(const void* in, void* out, const StepParams& p, hipStream_t 
 
 template <class S>
 hipError_t fixup_s(const void* in, void* out, const StepParams& p, hipStream_t s) {
-    if (p.wall_nodes == 0) return hipSuccess;
+    if (TSLB_FUSED_WALLS || p.wall_nodes == 0) return hipSuccess;  // the update did the bounce-back
     const FieldPtrs<typename S::T> f = field_ptrs<S>(in, out, p);
     const int block = 256;
     const unsigned grid = (unsigned)((p.wall_nodes + block - 1) / block);

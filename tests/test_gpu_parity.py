@@ -313,3 +313,43 @@ def test_paper_jet_full_size_sampled():
     inlet = post[:, 0]
     regen = oracle.ghost_fill(G, post, 11)[:, 0]
     assert np.abs(regen - inlet).max() < 1e-8
+
+
+DEGENERATE = [
+    ("one_node", (1, 1, 1), (0,) * 6),
+    ("one_fluid_node", (3, 3, 3), (1,) * 6),
+    ("thin_periodic", (2, 1, 5), (0,) * 6),
+    ("one_tile_plus_one", (65, 3, 4), (0, 0, 1, 1, 0, 0)),
+    ("single_column", (1, 64, 3), (0, 0, 1, 1, 0, 0)),
+    ("long_thin_ghosts", (200, 3, 3), (3, 3, 1, 1, 0, 0)),
+]
+
+
+@pytest.mark.parametrize("kernel", KERNELS)
+@pytest.mark.parametrize("name,dims,faces", DEGENERATE)
+def test_degenerate_grids(kernel, name, dims, faces):
+    """Axes of one node (every neighbour is the node itself), a single fluid
+    node between six walls, one column past a tile, one-column grids, and
+    zero steps; 1 and 4 steps against the oracle."""
+    nx, ny, nz = dims
+    case = W.Case(name, nx, ny, nz, 0.62, faces=faces, force=(2e-6, -1e-6, 0.0))
+    st0 = W.to_fp32(W.random_state(case.shape, seed=106))
+    G = oracle_grid(case)
+    st0 = oracle.ghost_fill(G, st0, 0)
+    kinds = oracle.node_kinds(G)
+    fl = kinds == 0
+    s = gpu_solver(case, kernel=kernel)
+    s.set_state(to_device_state(st0))
+    s.step(0)
+    assert s.t == 0
+    s.step(1)
+    got1 = from_device_state(s.get_state())
+    s.step(3)
+    got4 = from_device_state(s.get_state())
+    s.close()
+    want1 = oracle.step(G, st0)
+    want4 = oracle.run(G, st0, 4)
+    assert abs_err(got1[0], want1[0], fl) < 1e-7
+    assert rel_err(got1[1:4], want1[1:4], fl) < 2e-6
+    assert abs_err(got1[4:], want1[4:], fl) < pi_tol(want1[:, fl])
+    assert rel_err(got4[1:4], want4[1:4], fl) < 1e-5
