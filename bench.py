@@ -29,7 +29,7 @@ BYTES_PER_FIELD = {0: 4, 1: 2, 2: 2}
 
 # the sources the tiled update kernel is compiled from: HBM counters taken
 # with other sources are not reported as this kernel's traffic
-KERNEL_SOURCES = ("update_tiled.hip", "tslb_tiles.h", "tslb_device.h", "tslb_internal.h")
+KERNEL_SOURCES = ("update_tiled.hip", "tslb_tiles.h", "tslb_device.h", "tslb_params.h")
 
 
 def _source_hash():
@@ -367,8 +367,8 @@ def main():
         print(json.dumps({"copy_bytes_per_launch": 2 * n * 4, "launches": 20}))
         return
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build runs on a single MI355X and has no multi-GPU path "
-              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
+        print("bench.py measures one GPU: the library runs the update on a single MI355X and has no "
+              "multi-GPU path (--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

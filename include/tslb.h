@@ -46,7 +46,7 @@ enum { TSLB_D3Q27 = 27, TSLB_D3Q19 = 19, TSLB_D2Q9 = 9 };   /* lattices (Section
 enum { TSLB_FP32 = 0, TSLB_FP16 = 1, TSLB_BF16 = 2 };       /* moment storage; compute is FP32 */
 enum { TSLB_PERIODIC = 0, TSLB_WALL = 1, TSLB_INLET = 2, TSLB_OUTLET = 3 }; /* face kinds */
 enum { TSLB_DEVICE = 1, TSLB_RHO_DEVIATION = 2 };           /* set/get flags */
-enum { TSLB_OBJ_KINETIC_ENERGY = 0 };                       /* adjoint objectives */
+enum { TSLB_OBJ_KINETIC_ENERGY = 0, TSLB_OBJ_WALL_SHEAR = 1 }; /* adjoint objectives */
 enum { TSLB_STATS_PROFILE = 1, TSLB_STATS_FIELD = 2 };      /* statistics kinds (bit set) */
 enum {
     TSLB_OK = 0,
@@ -198,8 +198,19 @@ int tslb_adjoint_step(tslb_handle h, const void *state_t, const void *state_t1, 
 
 /* Seed of the adjoint: lam = dL/dM for the objective at a raw state
  * (TSLB_OBJ_KINETIC_ENERGY: L = 1/2 sum_fluid rho |u|^2, so lam_rho =
- * |u|^2 / 2, lam_u = rho u, lam_Pi = 0; zero on non-fluid nodes).          */
+ * |u|^2 / 2, lam_u = rho u, lam_Pi = 0; zero on non-fluid nodes.
+ * TSLB_OBJ_WALL_SHEAR: the x-directed viscous force on the walls normal to
+ * y and z, L = sum over fluid nodes next to such a wall face f of
+ * s_f sigma_xd, d the face's normal axis, s_f = +1 on the low and -1 on the
+ * high face, sigma = -(1 - omega/2) Pi^neq the viscous stress of the BGK
+ * update (Section 2); lam is -s_f (1 - omega/2) on Pi_xd of those nodes and
+ * zero elsewhere).                                                          */
 int tslb_adjoint_seed(tslb_handle h, const void *state, int objective, float *lam, void *stream);
+
+/* Value of an objective (as for tslb_adjoint_seed) at the current level,
+ * summed in FP64 in a fixed order.  Synchronises the stream.  Returns
+ * TSLB_E_UNSTABLE (with *out still written) if any fluid moment is NaN/Inf. */
+int tslb_objective(tslb_handle h, int objective, double *out, void *stream);
 
 /* Checkpointed rollout for gradients (recompute-every-K scheme).
  * tslb_rollout_workspace_bytes: device bytes needed for nsteps with a

@@ -134,7 +134,8 @@ def _load():
         "or_adjoint_step": (ctypes.c_int, [G, _D, _D, _D, _D, _D]),
         "or_adjoint_nodes": (ctypes.c_int, [G, _D, _D, _D, _L, ctypes.c_long, _D, _D]),
         "or_ke_seed": (ctypes.c_double, [G, _D, _D]),
-        "or_rollout_grad": (ctypes.c_int, [G, _D, _D, ctypes.c_long, ctypes.c_int, _D, _D, _D]),
+        "or_wall_shear_seed": (ctypes.c_double, [G, _D, _D]),
+        "or_rollout_grad": (ctypes.c_int, [G, _D, _D, ctypes.c_long, ctypes.c_int, ctypes.c_int, _D, _D, _D]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -325,14 +326,26 @@ def ke_seed(grid, st):
     return L, lam
 
 
-def rollout_grad(grid, st0, nsteps, g=None, t0=0):
-    """Loss L = 1/2 sum rho |u|^2 after nsteps, dL/dM_0 and dL/dg (FP64)."""
+def wall_shear_seed(grid, st):
+    """Wall shear objective (x force on the y and z walls) and dL/dM."""
+    st = _state(grid, st)
+    lam = np.empty_like(st)
+    L = _load().or_wall_shear_seed(ctypes.byref(grid), _p(st), _p(lam))
+    return L, lam
+
+
+OBJ_KINETIC_ENERGY, OBJ_WALL_SHEAR = 0, 1
+
+
+def rollout_grad(grid, st0, nsteps, g=None, t0=0, objective=OBJ_KINETIC_ENERGY):
+    """Loss L after nsteps (objective 0: 1/2 sum rho |u|^2; 1: the wall shear
+    force), dL/dM_0 and dL/dg (FP64)."""
     st0 = _state(grid, st0)
     g = _field(grid, g)
     loss = ctypes.c_double(0.0)
     lam0 = np.empty_like(st0)
     dg = np.zeros((3,) + grid.shape)
-    if _load().or_rollout_grad(ctypes.byref(grid), _p(st0), _p(g), t0, nsteps, ctypes.byref(loss), _p(lam0),
-                               _p(dg)) != 0:
+    if _load().or_rollout_grad(ctypes.byref(grid), _p(st0), _p(g), t0, nsteps, objective, ctypes.byref(loss),
+                               _p(lam0), _p(dg)) != 0:
         raise ValueError("oracle adjoint: unsupported grid (ghost layers)")
     return loss.value, lam0, dg

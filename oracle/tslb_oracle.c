@@ -636,11 +636,44 @@ double or_ke_seed(const or_grid *G, const double *st, double *lam)
     return L;
 }
 
+/* Wall shear objective: the x-directed viscous force on the walls normal to
+ * y and z, L = sum over fluid nodes next to such a wall face f of
+ * s_f sigma_xd, with d the face's normal axis, s_f = +1 on the low face and
+ * -1 on the high face, and the viscous stress of the BGK update
+ * sigma = -(1 - omega / 2) Pi^neq (Pi^neq the stored pre-collision
+ * non-equilibrium moment, omega that of the node).  L is linear in Pi, so
+ * lam = dL/dM is the constant -s_f (1 - omega / 2) on Pi_xd of those nodes
+ * (summed over the faces a node touches).  Returns L.                       */
+double or_wall_shear_seed(const or_grid *G, const double *st, double *lam)
+{
+    const long N = (long)G->nx * G->ny * G->nz;
+    double L = 0.0;
+    memset(lam, 0, sizeof(double) * 10 * N);
+    for (long n = 0; n < N; n++) {
+        if (node_kind(G, n) != NODE_FLUID) continue;
+        int x[3];
+        node_coords(G, n, x);
+        const double k = 1.0 - 0.5 * omega_at(G, n);
+        for (int f = 2; f < 6; f++) {
+            if (G->face[f] != FACE_WALL) continue;
+            const int d = f / 2;
+            const int layer = (f % 2 == 0) ? 1 : dim(G, d) - 2;
+            if (x[d] != layer) continue;
+            const double s = (f % 2 == 0) ? 1.0 : -1.0;
+            const int q = 4 + PI_IDX[0][d]; /* Pi_xy or Pi_xz */
+            L += -s * k * st[q * N + n];
+            lam[q * N + n] += -s * k;
+        }
+    }
+    return L;
+}
+
 /* Gradient of L(state after nsteps) with respect to the initial state and the
  * force field, by storing every level and sweeping the adjoint backwards.
+ * objective 0: kinetic energy (or_ke_seed); 1: wall shear (or_wall_shear_seed).
  * lam0 (10N) receives dL/dM_0; dg (3N, may be NULL) receives dL/dg.          */
-int or_rollout_grad(const or_grid *G, const double *st0, const double *gf, long t0, int nsteps, double *loss,
-                    double *lam0, double *dg)
+int or_rollout_grad(const or_grid *G, const double *st0, const double *gf, long t0, int nsteps, int objective,
+                    double *loss, double *lam0, double *dg)
 {
     if (G->lattice != 0 && G->lattice != 27) return -3; /* derivatives: D3Q27 only */
     lattice_init();
@@ -653,7 +686,8 @@ int or_rollout_grad(const or_grid *G, const double *st0, const double *gf, long 
     memcpy(traj, st0, sizeof(double) * 10 * N);
     for (int s = 0; s < nsteps; s++)
         step_r(G, traj + (size_t)s * 10 * N, traj + (size_t)(s + 1) * 10 * N, gf, t0 + s);
-    *loss = or_ke_seed(G, traj + (size_t)nsteps * 10 * N, lam);
+    *loss = objective == 1 ? or_wall_shear_seed(G, traj + (size_t)nsteps * 10 * N, lam)
+                           : or_ke_seed(G, traj + (size_t)nsteps * 10 * N, lam);
     if (dg) memset(dg, 0, sizeof(double) * 3 * N);
     for (int s = nsteps - 1; s >= 0; s--) {
         or_adjoint_step(G, traj + (size_t)s * 10 * N, gf, lam, tmp, dg);

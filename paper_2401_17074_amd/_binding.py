@@ -16,7 +16,7 @@ TSLB_D3Q27, TSLB_D3Q19, TSLB_D2Q9 = 27, 19, 9
 TSLB_FP32, TSLB_FP16, TSLB_BF16 = 0, 1, 2
 TSLB_PERIODIC, TSLB_WALL, TSLB_INLET, TSLB_OUTLET = 0, 1, 2, 3
 TSLB_DEVICE, TSLB_RHO_DEVIATION = 1, 2
-TSLB_OBJ_KINETIC_ENERGY = 0
+TSLB_OBJ_KINETIC_ENERGY, TSLB_OBJ_WALL_SHEAR = 0, 1
 TSLB_STATS_PROFILE, TSLB_STATS_FIELD = 1, 2
 TSLB_OK, TSLB_E_INVALID, TSLB_E_UNSUPPORTED, TSLB_E_NOMEM, TSLB_E_HIP, TSLB_E_UNSTABLE = 0, -1, -2, -3, -4, -5
 
@@ -48,6 +48,7 @@ SIGNATURES = {
     "tslb_get_moments": (_i, [_vp, _vp, _vp, _vp, _i, _vp]),
     "tslb_set_force_field": (_i, [_vp, _vp, _vp]),
     "tslb_step": (_i, [_vp, _i, _vp]),
+    "tslb_objective": (_i, [_vp, _i, ctypes.POINTER(ctypes.c_double), _vp]),
     "tslb_stats_begin": (_i, [_vp, _i, _i, _vp]),
     "tslb_stats_sample": (_i, [_vp, _vp]),
     "tslb_stats_profile": (_i, [_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64), _vp]),
@@ -179,6 +180,12 @@ def tslb_stats_field(h, mean_u, cov, stream=None):
 def tslb_stats_jet(h, axis, center, uc, rhalf, stream=None):
     c = (ctypes.c_float * 2)(*[float(v) for v in center])
     return _check(lib.tslb_stats_jet(h, axis, c, _ptr(uc), _ptr(rhalf), _stream(stream)))
+
+
+def tslb_objective(h, objective, stream=None):
+    out = ctypes.c_double()
+    _check(lib.tslb_objective(h, objective, ctypes.byref(out), _stream(stream)))
+    return out.value
 
 
 def tslb_set_relaxation_profile(h, tau_z, stream=None):

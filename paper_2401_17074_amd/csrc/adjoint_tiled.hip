@@ -106,9 +106,8 @@ __global__ void __launch_bounds__(NTHREADS, TSLB_WAVES_PER_EU)
     const unsigned long long N = (unsigned long long)g.N;
     const unsigned plane_nodes = (unsigned)nx * (unsigned)ny;
 
-    const int nblk = tiles_x * tiles_y * tiles_z;
-    int b = blockIdx.x;
-    if ((nblk & 7) == 0) b = (b & 7) * (nblk >> 3) + (b >> 3);
+    const int b = xcd_tile(blockIdx.x, tiles_x * tiles_y * tiles_z);
+    if (b < 0) return;  // padding block (before any barrier)
     const int tx = b % tiles_x;
     const int ty = (b / tiles_x) % tiles_y;
     const int tz = b / (tiles_x * tiles_y);
@@ -278,7 +277,7 @@ hipError_t launch_t(const float* st0, const float* st1, const float* lam1, float
     const int tiles_z = (p.geo.n[2] + TZ - 1) / TZ;
     const unsigned nblk = (unsigned)tiles_x * tiles_y * tiles_z;
     if (p.geo.N >= (1LL << 30)) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((adjoint_tiled_kernel<WALLS, FIELD, DG>), dim3(nblk), dim3(NTHREADS), 0, s, st0, st1, lam1,
+    hipLaunchKernelGGL((adjoint_tiled_kernel<WALLS, FIELD, DG>), dim3(xcd_grid(nblk)), dim3(NTHREADS), 0, s, st0, st1, lam1,
                        lam0, dg, p, tiles_x, tiles_y, tiles_z, TZ);
     return hipGetLastError();
 }

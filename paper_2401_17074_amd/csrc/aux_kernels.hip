@@ -128,6 +128,19 @@ __global__ void unpack_kernel(const typename S::T* __restrict__ st, float* __res
         for (int k = 0; k < 6; ++k) pi[k * N + n] = S::load(st[(4 + k) * N + n], p.inv_scale[2]);
 }
 
+// Weight of Pi_xd (d = 1: y, d = 2: z) in the wall shear objective at a
+// fluid node: the x force on the walls normal to axis d, sum of s_f sigma_xd
+// over the wall faces f the node is next to, with sigma = -(1 - omega/2) Pi
+// and s_f = +1 (low face) or -1 (high face).  1 - omega/2 = (1 + (1 - omega))/2.
+__device__ __forceinline__ double wall_shear_weight(const Geometry& g, const StepParams& p, int y, int z, int d) {
+    const int c = d == 1 ? y : z;
+    const double k = 0.5 * (1.0 + (double)omo_at(p, z));
+    double w = 0.0;
+    if (((g.lo_solid >> d) & 1) && c == 1) w -= k;
+    if (((g.hi_solid >> d) & 1) && c == g.n[d] - 2) w += k;
+    return w;
+}
+
 // ---------------------------------------------------------------- reductions
 // Two passes with a fixed order, so the FP64 sums are reproducible.
 constexpr int kRedThreads = 256;
@@ -136,7 +149,7 @@ template <class S>
 __global__ void __launch_bounds__(kRedThreads) reduce_partial_kernel(const typename S::T* __restrict__ st,
                                                                      double* __restrict__ partials, StepParams p) {
     const Geometry& g = p.geo;
-    double acc[6] = {0, 0, 0, 0, 0, 0};
+    double acc[kRedSums] = {0, 0, 0, 0, 0, 0, 0};
     for (long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x; n < g.N;
          n += (long long)gridDim.x * blockDim.x) {
         const int x = (int)(n % g.n[0]);
@@ -157,23 +170,24 @@ __global__ void __launch_bounds__(kRedThreads) reduce_partial_kernel(const typen
         acc[3] += rho * uz;
         acc[4] += 0.5 * rho * (ux * ux + uy * uy + uz * uz);
         acc[5] += bad ? 1.0 : 0.0;
+        acc[6] += wall_shear_weight(g, p, y, z, 1) * (double)m[7] + wall_shear_weight(g, p, y, z, 2) * (double)m[8];
     }
-    __shared__ double sh[6][kRedThreads];
-    for (int k = 0; k < 6; ++k) sh[k][threadIdx.x] = acc[k];
+    __shared__ double sh[kRedSums][kRedThreads];
+    for (int k = 0; k < kRedSums; ++k) sh[k][threadIdx.x] = acc[k];
     __syncthreads();
     for (int w = kRedThreads / 2; w > 0; w >>= 1) {
         if ((int)threadIdx.x < w)
-            for (int k = 0; k < 6; ++k) sh[k][threadIdx.x] += sh[k][threadIdx.x + w];
+            for (int k = 0; k < kRedSums; ++k) sh[k][threadIdx.x] += sh[k][threadIdx.x + w];
         __syncthreads();
     }
     if (threadIdx.x == 0)
-        for (int k = 0; k < 6; ++k) partials[k * gridDim.x + blockIdx.x] = sh[k][0];
+        for (int k = 0; k < kRedSums; ++k) partials[k * gridDim.x + blockIdx.x] = sh[k][0];
 }
 
 __global__ void __launch_bounds__(kRedThreads) reduce_final_kernel(const double* __restrict__ partials, int nblocks,
                                                                    double* __restrict__ out6) {
     __shared__ double sh[kRedThreads];
-    for (int k = 0; k < 6; ++k) {
+    for (int k = 0; k < kRedSums; ++k) {
         double a = 0.0;
         for (int b = threadIdx.x; b < nblocks; b += blockDim.x) a += partials[k * nblocks + b];
         sh[threadIdx.x] = a;
@@ -188,8 +202,11 @@ __global__ void __launch_bounds__(kRedThreads) reduce_final_kernel(const double*
 }
 
 // ---------------------------------------------------------------- adjoint
-// Seed of the kinetic-energy objective L = 1/2 sum_fluid rho |u|^2.
-__global__ void adjoint_seed_kernel(const float* __restrict__ st, float* __restrict__ lam, StepParams p) {
+// Seeds lam = dL/dM of the objectives: kinetic energy
+// L = 1/2 sum_fluid rho |u|^2, or the wall shear force (linear in Pi: the
+// weight of Pi_xy / Pi_xz at the wall-adjacent layers, zero elsewhere).
+__global__ void adjoint_seed_kernel(const float* __restrict__ st, float* __restrict__ lam, StepParams p,
+                                    int objective) {
     const Geometry& g = p.geo;
     const long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (n >= g.N) return;
@@ -197,6 +214,15 @@ __global__ void adjoint_seed_kernel(const float* __restrict__ st, float* __restr
     const int y = (int)((n / g.n[0]) % g.n[1]);
     const int z = (int)(n / ((long long)g.n[0] * g.n[1]));
     const bool fl = is_fluid(g, x, y, z);
+    if (objective == 1) {
+#pragma unroll
+        for (int k = 0; k < 10; ++k) lam[k * g.N + n] = 0.0f;
+        if (fl) {
+            lam[7 * g.N + n] = (float)wall_shear_weight(g, p, y, z, 1);
+            lam[8 * g.N + n] = (float)wall_shear_weight(g, p, y, z, 2);
+        }
+        return;
+    }
     const float rho = 1.0f + st[n];
     const float ux = st[g.N + n], uy = st[2 * g.N + n], uz = st[3 * g.N + n];
     lam[n] = fl ? 0.5f * (ux * ux + uy * uy + uz * uz) : 0.0f;
@@ -400,10 +426,10 @@ hipError_t launch_reduce(int storage, const void* st, double* partials, int nblo
     return hipGetLastError();
 }
 
-hipError_t launch_adjoint_seed(const float* st, float* lam, const StepParams& p, hipStream_t s) {
+hipError_t launch_adjoint_seed(const float* st, float* lam, const StepParams& p, int objective, hipStream_t s) {
     const int block = 256;
     const unsigned grid = (unsigned)((p.geo.N + block - 1) / block);
-    hipLaunchKernelGGL(adjoint_seed_kernel, dim3(grid), dim3(block), 0, s, st, lam, p);
+    hipLaunchKernelGGL(adjoint_seed_kernel, dim3(grid), dim3(block), 0, s, st, lam, p, objective);
     return hipGetLastError();
 }
 

@@ -182,9 +182,9 @@ int tslb_create(int nx, int ny, int nz, int lattice, float tau, const float forc
     h->red_blocks = 1024;
     const size_t bytes = h->elem_bytes * 10 * (size_t)g.N;
     if (hipMalloc(&h->buf[0], bytes) != hipSuccess || hipMalloc(&h->buf[1], bytes) != hipSuccess ||
-        hipMalloc((void**)&h->red_partials, sizeof(double) * 6 * h->red_blocks) != hipSuccess ||
-        hipMalloc((void**)&h->red_out, sizeof(double) * 6) != hipSuccess ||
-        (h->p.wall_nodes > 0 &&
+        hipMalloc((void**)&h->red_partials, sizeof(double) * kRedSums * h->red_blocks) != hipSuccess ||
+        hipMalloc((void**)&h->red_out, sizeof(double) * kRedSums) != hipSuccess ||
+        (h->p.wall_nodes > 0 && tiled_uses_wall_side() &&
          hipMalloc((void**)&h->p.wall_side, sizeof(float) * 10 * (size_t)h->p.wall_nodes) != hipSuccess)) {
         tslb_destroy(h);
         return fail(TSLB_E_NOMEM, "device allocation of 2 x %zu bytes failed", bytes);
@@ -498,11 +498,26 @@ int tslb_reduce(tslb_handle h, double out[5], void* stream) {
     if (!h || !out) return fail(TSLB_E_INVALID, "NULL handle or output");
     DeviceGuard dg(h->device);
     hipStream_t s = S(stream);
-    double host[6];
+    double host[kRedSums];
     HIP_TRY(launch_reduce(h->storage, h->buf[h->cur], h->red_partials, h->red_blocks, h->red_out, h->p, s));
     HIP_TRY(hipMemcpyAsync(host, h->red_out, sizeof host, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     for (int k = 0; k < 5; ++k) out[k] = host[k];
+    if (host[5] != 0.0) return fail(TSLB_E_UNSTABLE, "%.0f fluid nodes hold NaN or Inf moments", host[5]);
+    return TSLB_OK;
+}
+
+int tslb_objective(tslb_handle h, int objective, double* out, void* stream) {
+    if (!h || !out) return fail(TSLB_E_INVALID, "NULL handle or output");
+    if (objective != TSLB_OBJ_KINETIC_ENERGY && objective != TSLB_OBJ_WALL_SHEAR)
+        return fail(TSLB_E_UNSUPPORTED, "objective %d", objective);
+    DeviceGuard dg(h->device);
+    hipStream_t s = S(stream);
+    double host[kRedSums];
+    HIP_TRY(launch_reduce(h->storage, h->buf[h->cur], h->red_partials, h->red_blocks, h->red_out, h->p, s));
+    HIP_TRY(hipMemcpyAsync(host, h->red_out, sizeof host, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    *out = objective == TSLB_OBJ_WALL_SHEAR ? host[6] : host[4];
     if (host[5] != 0.0) return fail(TSLB_E_UNSTABLE, "%.0f fluid nodes hold NaN or Inf moments", host[5]);
     return TSLB_OK;
 }
@@ -526,10 +541,11 @@ int tslb_load_state(tslb_handle h, const void* src, void* stream) {
 
 int tslb_adjoint_seed(tslb_handle h, const void* state, int objective, float* lam, void* stream) {
     if (!h || !state || !lam) return fail(TSLB_E_INVALID, "NULL argument");
-    if (objective != TSLB_OBJ_KINETIC_ENERGY) return fail(TSLB_E_UNSUPPORTED, "objective %d", objective);
+    if (objective != TSLB_OBJ_KINETIC_ENERGY && objective != TSLB_OBJ_WALL_SHEAR)
+        return fail(TSLB_E_UNSUPPORTED, "objective %d", objective);
     if (h->storage != TSLB_FP32) return fail(TSLB_E_UNSUPPORTED, "the adjoint needs FP32 storage");
     DeviceGuard dg(h->device);
-    HIP_TRY(launch_adjoint_seed((const float*)state, lam, h->p, S(stream)));
+    HIP_TRY(launch_adjoint_seed((const float*)state, lam, h->p, objective, S(stream)));
     return TSLB_OK;
 }
 

@@ -359,6 +359,18 @@ constexpr int kBlocksPerCu = (163840 / kLdsBytes) < ((4 * TSLB_WAVES_PER_EU) / (
                                  : ((4 * TSLB_WAVES_PER_EU) / (NTHREADS / 64));
 static_assert(kBlocksPerCu >= 1, "a tile must fit one CU");
 
+// Consecutive block ids are dealt round-robin to the 8 XCDs.  The launch is
+// padded to a multiple of 8 blocks and block b takes tile
+// (b % 8) * (padded / 8) + b / 8, so each XCD gets a contiguous run of
+// tiles (x fastest, then y, then z: tiles that run together on one XCD are
+// neighbours sharing halo columns in its L2); padding blocks get -1.
+__device__ __forceinline__ int xcd_tile(int b, int nblk) {
+    const int per = (nblk + 7) >> 3;
+    const int t = (b & 7) * per + (b >> 3);
+    return t < nblk ? t : -1;
+}
+inline unsigned xcd_grid(int nblk) { return (unsigned)((nblk + 7) & ~7); }
+
 inline int compute_units() {
     static int cus = 0;
     if (cus == 0) {

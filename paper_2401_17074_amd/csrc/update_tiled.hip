@@ -44,9 +44,8 @@ __global__ void __launch_bounds__(NTHREADS, TSLB_WAVES_PER_EU) update_tiled_kern
     // the tiles that run together on one XCD are x and y neighbours marching
     // the same planes: the halo columns and rows they read from each other
     // are then L2 hits instead of HBM reads.
-    const int nblk = tiles_x * tiles_y * tiles_z;
-    int b = blockIdx.x;
-    if ((nblk & 7) == 0) b = (b & 7) * (nblk >> 3) + (b >> 3);
+    const int b = xcd_tile(blockIdx.x, tiles_x * tiles_y * tiles_z);
+    if (b < 0) return;  // padding block (before any barrier)
     const int tx = b % tiles_x;
     const int ty = (b / tiles_x) % tiles_y;
     const int tz = b / (tiles_x * tiles_y);
@@ -319,7 +318,7 @@ hipError_t launch_t(const void* in, void* out, const StepParams& p, hipStream_t 
     const unsigned nblk = (unsigned)tiles_x * tiles_y * tiles_z;
     if (p.geo.N >= (1LL << 30)) return hipErrorInvalidValue;  // 32-bit node offsets
     const FieldPtrs<typename S::T> f = field_ptrs<S>(in, out, p);
-    hipLaunchKernelGGL((update_tiled_kernel<S, WALLS, FIELD, ORDER, LAT>), dim3(nblk), dim3(NTHREADS), 0, s, f, p, tiles_x,
+    hipLaunchKernelGGL((update_tiled_kernel<S, WALLS, FIELD, ORDER, LAT>), dim3(xcd_grid(nblk)), dim3(NTHREADS), 0, s, f, p, tiles_x,
                        tiles_y, tiles_z, TZ);
     return hipGetLastError();
 }
@@ -365,6 +364,8 @@ hipError_t fixup_s(const void* in, void* out, const StepParams& p, hipStream_t s
     }
     return hipGetLastError();
 }
+
+bool tiled_uses_wall_side() { return TSLB_FUSED_WALLS == 0; }
 
 hipError_t launch_wall_fixup(int storage, const void* in, void* out, const StepParams& p, hipStream_t s) {
     switch (storage) {

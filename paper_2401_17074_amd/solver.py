@@ -139,23 +139,30 @@ class Solver:
         C.tslb_adjoint_step(self.h, raw_t, raw_t1, lam_t1, lam_t, dg)
         return lam_t
 
-    def adjoint_seed(self, raw):
+    def adjoint_seed(self, raw, objective=C.TSLB_OBJ_KINETIC_ENERGY):
         lam = torch.empty((10,) + self.shape, dtype=torch.float32, device=self.device)
-        C.tslb_adjoint_seed(self.h, raw, lam)
+        C.tslb_adjoint_seed(self.h, raw, lam, objective)
         return lam
+
+    def objective(self, objective=C.TSLB_OBJ_KINETIC_ENERGY):
+        """Value of an objective at the current level (FP64)."""
+        return C.tslb_objective(self.h, objective)
 
 
 class TslbRollout(torch.autograd.Function):
-    """L = 1/2 sum rho |u|^2 after `nsteps` steps from (rho = 1, u0, Pi = 0)
-    under the force field g, with checkpoints every `every` steps.
+    """L after `nsteps` steps from (rho = 1, u0, Pi = 0) under the force field
+    g, with checkpoints every `every` steps; L is the kinetic energy
+    1/2 sum rho |u|^2 (TSLB_OBJ_KINETIC_ENERGY, the default) or the wall
+    shear force on the y and z walls (TSLB_OBJ_WALL_SHEAR).
 
-    forward(g (3, nz, ny, nx), u0 (3, nz, ny, nx), solver, nsteps, every) -> L
-    (float64 scalar); backward returns dL/dg and dL/du0 from the library's
-    discrete adjoint, recomputing each checkpointed segment once.
+    forward(g (3, nz, ny, nx), u0 (3, nz, ny, nx), solver, nsteps, every
+    [, objective]) -> L (float64 scalar); backward returns dL/dg and dL/du0
+    from the library's discrete adjoint, recomputing each checkpointed
+    segment once.
     """
 
     @staticmethod
-    def forward(ctx, g, u0, solver, nsteps, every):
+    def forward(ctx, g, u0, solver, nsteps, every, objective=C.TSLB_OBJ_KINETIC_ENERGY):
         st = torch.zeros((10,) + solver.shape, dtype=torch.float32, device=solver.device)
         st[1:4] = u0.detach().to(torch.float32)
         solver.t = 0
@@ -165,17 +172,17 @@ class TslbRollout(torch.autograd.Function):
         ws = torch.empty(nbytes, dtype=torch.uint8, device=solver.device)
         C.tslb_rollout_forward(solver.h, nsteps, every, ws)
         final = solver.save_raw()
-        (mass, px, py, pz, ke), _ = solver.reduce()
-        ctx.solver, ctx.nsteps, ctx.every = solver, nsteps, every
+        loss = solver.objective(objective)
+        ctx.solver, ctx.nsteps, ctx.every, ctx.objective = solver, nsteps, every, objective
         ctx.save_for_backward(ws, final)
-        return torch.tensor(ke, dtype=torch.float64, device=solver.device)
+        return torch.tensor(loss, dtype=torch.float64, device=solver.device)
 
     @staticmethod
     def backward(ctx, dL):
         ws, final = ctx.saved_tensors
         solver = ctx.solver
-        lam = solver.adjoint_seed(final)
+        lam = solver.adjoint_seed(final, ctx.objective)
         dg = torch.zeros((3,) + solver.shape, dtype=torch.float32, device=solver.device)
         C.tslb_rollout_backward(solver.h, ctx.nsteps, ctx.every, ws, lam, dg)
         scale = dL.to(torch.float32)
-        return dg * scale, lam[1:4] * scale, None, None, None
+        return dg * scale, lam[1:4] * scale, None, None, None, None

@@ -130,3 +130,37 @@ def test_adjoint_step_with_relaxation_profile(faces, kernel):
     want_lam, want_dg = oracle.adjoint_step(G, st0, lam1, g)
     assert _rel(lam0, want_lam) < 1e-5
     assert _rel(dg, want_dg) < 1e-5
+
+
+@pytest.mark.parametrize("kernel", [0, 1])
+def test_wall_shear_objective_rollout_matches_oracle(kernel):
+    """The wall shear force on the y and z walls of a small forced channel:
+    its value, its seed, and TslbRollout's gradients (20 steps, checkpoint
+    every 6) against the oracle's stored-trajectory adjoint."""
+    import torch
+    from paper_2401_17074_amd import TslbRollout
+    from paper_2401_17074_amd import capi as C
+    case = W.Case("ws", 24, 18, 14, 0.7, faces=(0, 0, 1, 1, 1, 1))
+    g = W.random_force(case.shape, seed=221, amp=1e-4).astype(np.float32).astype(np.float64)
+    u0 = W.random_state(case.shape, seed=222, u_amp=0.02, pi_amp=0.0)[1:4].astype(np.float32).astype(np.float64)
+    G = oracle_grid(case)
+    kinds = oracle.node_kinds(G)
+    u0[:, kinds != 0] = 0.0
+    st0 = W.rest_state(case.shape)
+    st0[1:4] = u0
+    L_or, lam0_or, dg_or = oracle.rollout_grad(G, st0, 20, g, objective=oracle.OBJ_WALL_SHEAR)
+    s = gpu_solver(case, kernel=kernel)
+    # value and seed of the objective at the initial state
+    s.set_state(to_device_state(st0))
+    assert s.objective(C.TSLB_OBJ_WALL_SHEAR) == pytest.approx(oracle.wall_shear_seed(G, st0)[0], abs=1e-12)
+    lam = s.adjoint_seed(s.save_raw(), C.TSLB_OBJ_WALL_SHEAR).double().cpu().numpy()
+    assert np.abs(lam - oracle.wall_shear_seed(G, st0)[1]).max() < 1e-7
+    gt = torch.tensor(g, dtype=torch.float32, device="cuda", requires_grad=True)
+    ut = torch.tensor(u0, dtype=torch.float32, device="cuda", requires_grad=True)
+    L = TslbRollout.apply(gt, ut, s, 20, 6, C.TSLB_OBJ_WALL_SHEAR)
+    L.backward()
+    s.close()
+    assert float(L) == pytest.approx(L_or, rel=1e-4)
+    assert _rel(gt.grad.double().cpu().numpy(), dg_or) < 1e-4
+    fl = kinds == 0
+    assert _rel(ut.grad.double().cpu().numpy()[:, fl], lam0_or[1:4][:, fl]) < 1e-4

@@ -1,5 +1,5 @@
 """GPU parity of the forward update against the FP64 oracle (all through the
-C ABI).  Tolerances: the spec bar is max relative error <= 1e-5 in
+C ABI).  Tolerances: the parity bar is max relative error <= 1e-5 in
 rho and u after 100 laminar steps (Taylor-Green 32^3); single steps from the
 same binary32 state are held to a few binary32 ulps of the largest value
 (normwise 2e-6 for u, 1e-7 absolute for rho - 1; Pi^neq is the difference

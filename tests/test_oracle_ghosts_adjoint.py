@@ -234,3 +234,47 @@ def test_gaussian_inlet_ghost_velocity(oracle):
             else:
                 assert np.all(st[1:4, 0, y, x] == 0.0)
     assert hit == 21 and kinds[0].max() == 2
+
+
+def test_wall_shear_objective_of_poiseuille_flow(oracle):
+    """Steady Poiseuille flow between half-way walls (y = 1/2, ny - 3/2) has
+    sigma_xy = g (y_c - y) with y_c = (ny - 1)/2, so the x force the
+    objective measures at the two wall-adjacent layers (y = 1, ny - 2) is
+    2 A g (ny - 3) / 2 = g A (ny - 3) for A = nx nz nodes per layer; its
+    gradient is -s (1 - omega/2) on Pi_xy of those layers only."""
+    ny, g, tau = 12, 1e-6, 0.9
+    G = oracle.make_grid(2, ny, 3, tau, faces=(0, 0, 1, 1, 0, 0), force=(g, 0, 0))
+    out = oracle.run(G, W.rest_state(G.shape), 6000)
+    L, lam = oracle.wall_shear_seed(G, out)
+    assert L == pytest.approx(g * 2 * 3 * (ny - 3), rel=1e-9)
+    k = 1.0 - 0.5 / tau
+    assert np.all(lam[7, :, 1, :] == -k) and np.all(lam[7, :, ny - 2, :] == k)
+    lam[7, :, 1, :] = 0.0
+    lam[7, :, ny - 2, :] = 0.0
+    assert np.all(lam == 0.0)
+
+
+def test_wall_shear_rollout_gradient_matches_central_differences(oracle):
+    """FP64 central differences of the wall shear objective after 8 steps of
+    a small channel (walls on y and z) along random directions of the force
+    field and of the initial velocity."""
+    G = oracle.make_grid(5, 7, 6, 0.7, faces=(0, 0, 1, 1, 1, 1))
+    st0 = W.random_state(G.shape, seed=41, u_amp=0.03, pi_amp=1e-3)
+    g = W.random_force(G.shape, seed=42, amp=1e-3)
+    L, lam0, dg = oracle.rollout_grad(G, st0, 8, g, objective=oracle.OBJ_WALL_SHEAR)
+    rng = np.random.default_rng(43)
+
+    def loss(s, gf):
+        return oracle.wall_shear_seed(G, oracle.run(G, s, 8, gf))[0]
+
+    assert L == pytest.approx(loss(st0, g), rel=1e-14)
+    for _ in range(2):
+        d = rng.standard_normal(g.shape)
+        h = 1e-4 * np.abs(g).max()
+        fd = (loss(st0, g + h * d) - loss(st0, g - h * d)) / (2 * h)
+        assert (dg * d).sum() == pytest.approx(fd, rel=1e-6)
+        du = np.zeros_like(st0)
+        du[1:4] = rng.standard_normal((3,) + G.shape)
+        h = 1e-4 * np.abs(st0[1:4]).max()
+        fd = (loss(st0 + h * du, g) - loss(st0 - h * du, g)) / (2 * h)
+        assert (lam0 * du).sum() == pytest.approx(fd, rel=1e-6)
