@@ -183,6 +183,16 @@ size_t tslb_state_bytes(tslb_handle h);
 int tslb_save_state(tslb_handle h, void *dst, void *stream);
 int tslb_load_state(tslb_handle h, const void *src, void *stream);
 
+/* Hand the two state buffers to caller-owned device memory (e.g. tensors
+ * from PyTorch's allocator): buf0 and buf1 each hold tslb_state_bytes(h)
+ * bytes, 256-byte aligned, distinct, on the handle's device, and must stay
+ * alive until tslb_destroy or the next tslb_bind_state.  Both current
+ * buffers are copied over (the current level into buf0, so wall and ghost
+ * layers keep their contents), the stream is synchronised, and buffers the
+ * library allocated itself are freed; bound buffers are never freed by the
+ * library.  Errors: TSLB_E_INVALID (NULL, aliasing or misaligned buffers). */
+int tslb_bind_state(tslb_handle h, void *buf0, void *buf1, void *stream);
+
 /* Discrete adjoint (reverse-mode derivative) of one update step, the
  * transpose of the Section 2.2 update linearised at state_t:
  *   lam_t    = (dM_{t+1}/dM_t)^T lam_t1

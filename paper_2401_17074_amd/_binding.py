@@ -48,6 +48,7 @@ SIGNATURES = {
     "tslb_get_moments": (_i, [_vp, _vp, _vp, _vp, _i, _vp]),
     "tslb_set_force_field": (_i, [_vp, _vp, _vp]),
     "tslb_step": (_i, [_vp, _i, _vp]),
+    "tslb_bind_state": (_i, [_vp, _vp, _vp, _vp]),
     "tslb_objective": (_i, [_vp, _i, ctypes.POINTER(ctypes.c_double), _vp]),
     "tslb_stats_begin": (_i, [_vp, _i, _i, _vp]),
     "tslb_stats_sample": (_i, [_vp, _vp]),
@@ -180,6 +181,10 @@ def tslb_stats_field(h, mean_u, cov, stream=None):
 def tslb_stats_jet(h, axis, center, uc, rhalf, stream=None):
     c = (ctypes.c_float * 2)(*[float(v) for v in center])
     return _check(lib.tslb_stats_jet(h, axis, c, _ptr(uc), _ptr(rhalf), _stream(stream)))
+
+
+def tslb_bind_state(h, buf0, buf1, stream=None):
+    return _check(lib.tslb_bind_state(h, _ptr(buf0), _ptr(buf1), _stream(stream)))
 
 
 def tslb_objective(h, objective, stream=None):

@@ -146,6 +146,7 @@ int tslb_create(int nx, int ny, int nz, int lattice, float tau, const float forc
     g.N = (long long)nx * ny * nz;
     h->p.one_minus_omega = (float)(1.0 - 1.0 / (double)tau);
     h->p.order = b.order;
+    h->buf_owned = true;
     h->p.dims = lattice == TSLB_D2Q9 ? 2 : 3;
     h->p.lattice = lattice;
     h->lattice = lattice;
@@ -203,8 +204,10 @@ int tslb_destroy(tslb_handle h) {
     if (!h) return TSLB_OK;
     DeviceGuard dg(h->device);
     (void)hipDeviceSynchronize();
-    (void)hipFree(h->buf[0]);
-    (void)hipFree(h->buf[1]);
+    if (h->buf_owned) {
+        (void)hipFree(h->buf[0]);
+        (void)hipFree(h->buf[1]);
+    }
     (void)hipFree(h->gfield);
     (void)hipFree(h->staging);
     (void)hipFree(h->red_partials);
@@ -319,6 +322,29 @@ int tslb_set_relaxation_profile(tslb_handle h, const float* tau_z, void* stream)
     HIP_TRY(hipMemcpyAsync(h->omo_z, omo.data(), sizeof(float) * (size_t)nz, hipMemcpyHostToDevice, S(stream)));
     HIP_TRY(hipStreamSynchronize(S(stream)));
     h->p.omo_z = h->omo_z;
+    return TSLB_OK;
+}
+
+int tslb_bind_state(tslb_handle h, void* buf0, void* buf1, void* stream) {
+    if (!h || !buf0 || !buf1 || buf0 == buf1) return fail(TSLB_E_INVALID, "NULL or aliasing state buffers");
+    if (((uintptr_t)buf0 & 255) || ((uintptr_t)buf1 & 255))
+        return fail(TSLB_E_INVALID, "state buffers must be 256-byte aligned");
+    const size_t bytes = tslb_state_bytes(h);
+    const char *b0 = (const char*)buf0, *b1 = (const char*)buf1;
+    if (b0 < b1 + bytes && b1 < b0 + bytes) return fail(TSLB_E_INVALID, "state buffers overlap");
+    DeviceGuard dg(h->device);
+    hipStream_t s = S(stream);
+    HIP_TRY(hipMemcpyAsync(buf0, h->buf[h->cur], bytes, hipMemcpyDeviceToDevice, s));
+    HIP_TRY(hipMemcpyAsync(buf1, h->buf[1 - h->cur], bytes, hipMemcpyDeviceToDevice, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (h->buf_owned) {
+        (void)hipFree(h->buf[0]);
+        (void)hipFree(h->buf[1]);
+    }
+    h->buf[0] = buf0;
+    h->buf[1] = buf1;
+    h->cur = 0;
+    h->buf_owned = false;
     return TSLB_OK;
 }
 

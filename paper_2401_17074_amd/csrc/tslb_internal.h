@@ -56,6 +56,7 @@ struct tslb_ctx {
     int storage;
     size_t elem_bytes;       // bytes per stored value
     void* buf[2];            // ping-pong raw states, 10 N values each
+    bool buf_owned;          // false once tslb_bind_state handed them to the caller
     int cur;                 // index of the buffer holding the current level
     float* gfield;           // owned copy of the per-node force field (or null)
     float* staging;          // device staging for host set/get (10 N floats, lazily)

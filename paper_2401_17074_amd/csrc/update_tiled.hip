@@ -119,6 +119,21 @@ __global__ void __launch_bounds__(NTHREADS, TSLB_WAVES_PER_EU) update_tiled_kern
     if (TSLB_PREFETCH_DEPTH == 2 && active)
         load_node<S>(f, col + plane_nodes * (unsigned)plane_index(zs, nz, pz), p, m_ahead);
 
+    // Finalised moments of one output node, stored at byte offset pend_on.
+    constexpr bool kDefer = TSLB_DEFER_STORE < 0 ? WALLS : TSLB_DEFER_STORE != 0;
+    float pend[10];
+    unsigned pend_on = 0;
+    bool pend_valid = false;
+    auto store_pending = [&]() {
+        if (!pend_valid) return;
+        store_out(at(f.out[0], pend_on), S::store(pend[0], p.scale[0]));
+#pragma unroll
+        for (int q = 1; q < 4; ++q) store_out(at(f.out[q], pend_on), S::store(pend[q], p.scale[1]));
+#pragma unroll
+        for (int q = 4; q < 10; ++q) store_out(at(f.out[q], pend_on), S::store(pend[q], p.scale[2]));
+        pend_valid = false;
+    };
+
     // One plane zp with moments mcur: prefetch the next plane into mnext,
     // build and publish this plane's populations, add what arrives from it
     // to the output planes zp - 1 (aprev), zp (acur) and zp + 1 (anext, which
@@ -163,6 +178,8 @@ __global__ void __launch_bounds__(NTHREADS, TSLB_WAVES_PER_EU) update_tiled_kern
             Unroll<0, 27>::run([&]<int I>() {
                 if constexpr (cx_of(I) != 0 || cy_of(I) != 0) lds[slot_of(I)][ly][lx] = G[I];
             });
+            // the previous plane's outputs go out while this plane is built
+            if (kDefer) store_pending();
             // prefetch the next plane once this plane's moments are consumed;
             // the loads are in flight across the exchange and the gather
             // (mcur is dead once the coefficients are formed, so the next
@@ -211,14 +228,10 @@ __global__ void __launch_bounds__(NTHREADS, TSLB_WAVES_PER_EU) update_tiled_kern
 #pragma unroll
                 for (int k = 0; k < 6; ++k) side[4 + k] = aprev.s[k];
             } else if (fl) {
-                float m[10];
-                finalize<LAT == 19 ? 36 : 216>(aprev, m);
-                const unsigned on = (col + plane_nodes * (unsigned)zo) * (unsigned)sizeof(typename S::T);
-                store_out(at(f.out[0], on), S::store(m[0], p.scale[0]));
-#pragma unroll
-                for (int q = 1; q < 4; ++q) store_out(at(f.out[q], on), S::store(m[q], p.scale[1]));
-#pragma unroll
-                for (int q = 4; q < 10; ++q) store_out(at(f.out[q], on), S::store(m[q], p.scale[2]));
+                finalize<LAT == 19 ? 36 : 216>(aprev, pend);
+                pend_on = (col + plane_nodes * (unsigned)zo) * (unsigned)sizeof(typename S::T);
+                pend_valid = true;
+                if (!kDefer) store_pending();
             }
         }
         if (TSLB_PREFETCH_DEPTH == 2) {
@@ -246,6 +259,7 @@ __global__ void __launch_bounds__(NTHREADS, TSLB_WAVES_PER_EU) update_tiled_kern
         if (zp + 2 > ze) break;
         plane(zp + 2, a2, a0, a1);
     }
+    store_pending();
 }
 
 // Completes the fluid nodes next to a wall after the tiled update: adds the

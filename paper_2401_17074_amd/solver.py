@@ -41,6 +41,14 @@ class Solver:
         except Exception:
             pass
 
+    def bind_state_to_torch(self):
+        """Move the two state buffers into tensors from PyTorch's allocator
+        (kept on the Solver as `state_buffers`)."""
+        nb = C.tslb_state_bytes(self.h)
+        bufs = [torch.empty(nb, dtype=torch.uint8, device=self.device) for _ in range(2)]
+        C.tslb_bind_state(self.h, bufs[0], bufs[1])
+        self.state_buffers = bufs
+
     def set_kernel(self, variant):
         C.tslb_set_kernel(self.h, variant)
 

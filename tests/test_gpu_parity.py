@@ -229,6 +229,38 @@ def test_timed_steps_match_plain_steps(kernel):
 
 
 @pytest.mark.parametrize("kernel", KERNELS)
+def test_bound_state_buffers(kernel):
+    """After tslb_bind_state the solver runs on caller-owned tensors: the
+    bound buffer holds the current level (ghost layers included) and the
+    steps that follow match a solver on the library's own buffers bit for
+    bit.  Aliasing and misaligned buffers are rejected."""
+    import torch
+    from paper_2401_17074_amd import _binding as C
+    case = W.jet_case(nx=40, ny=22, nz=20, D=6.0, steps=12)
+    G = oracle_grid(case)
+    st0 = W.to_fp32(oracle.ghost_fill(G, W.jet_state(case), 0))
+    out = []
+    for bind in (False, True):
+        s = gpu_solver(case, kernel=kernel)
+        s.set_state(to_device_state(st0))
+        s.step(3)
+        if bind:
+            before = s.save_raw()
+            s.bind_state_to_torch()
+            assert torch.equal(s.state_buffers[0], before)
+            nb = C.tslb_state_bytes(s.h)
+            spare = torch.empty(nb + 256, dtype=torch.uint8, device="cuda")
+            with pytest.raises(RuntimeError):
+                C.tslb_bind_state(s.h, spare, spare)
+            with pytest.raises(RuntimeError):
+                C.tslb_bind_state(s.h, spare[4:], s.state_buffers[1])
+        s.step(case.steps - 3)
+        out.append(s.get_state().cpu().numpy())
+        s.close()
+    assert np.array_equal(out[0], out[1])
+
+
+@pytest.mark.parametrize("kernel", KERNELS)
 @pytest.mark.parametrize("name,faces", CASES[:3])
 def test_relaxation_profile_ragged_grid(kernel, name, faces):
     """A relaxation time that changes from plane to plane (each population
