@@ -48,6 +48,7 @@ enum { TSLB_PERIODIC = 0, TSLB_WALL = 1, TSLB_INLET = 2, TSLB_OUTLET = 3 }; /* f
 enum { TSLB_DEVICE = 1, TSLB_RHO_DEVIATION = 2 };           /* set/get flags */
 enum { TSLB_OBJ_KINETIC_ENERGY = 0, TSLB_OBJ_WALL_SHEAR = 1 }; /* adjoint objectives */
 enum { TSLB_STATS_PROFILE = 1, TSLB_STATS_FIELD = 2 };      /* statistics kinds (bit set) */
+#define TSLB_MAX_NODES (1LL << 30)                           /* nx*ny*nz must stay below this */
 enum {
     TSLB_OK = 0,
     TSLB_E_INVALID = -1,     /* bad argument (tau <= 1/2, dims, unpaired periodic faces, ...) */
@@ -112,12 +113,15 @@ typedef struct {
  *   nz = 1, periodic z faces and zero z components of force and inlet
  *   velocity; the state keeps the ten-field layout with u_z and the Pi
  *   components xz, yz, zz held at zero; one update kernel, no adjoint).
+ * nx*ny*nz must stay below TSLB_MAX_NODES = 2^30 (the kernels address each
+ *   field with 32-bit byte offsets; 2^30 nodes hold 86 GB of FP32 state).
  * tau: relaxation time, nu = (tau - 1/2) / 3 (Section 2), must exceed 1/2.
  * force: uniform body acceleration g (Section 3.1 forcing), may be NULL (0).
  * bc: may be NULL (all faces periodic, FP32 storage).
  * Allocates two state buffers on the current HIP device, sets the rest
  * state rho = 1, u = 0, Pi^neq = 0 at level t = 0, and synchronises.
- * Errors: TSLB_E_INVALID, TSLB_E_UNSUPPORTED (other lattices), TSLB_E_NOMEM. */
+ * Errors: TSLB_E_INVALID (also for too many nodes), TSLB_E_UNSUPPORTED
+ * (other lattices), TSLB_E_NOMEM.                                            */
 int tslb_create(int nx, int ny, int nz, int lattice, float tau, const float force[3], const tslb_bc *bc,
                 tslb_handle *out);
 
@@ -229,8 +233,9 @@ int tslb_objective(tslb_handle h, int objective, double *out, void *stream);
  * segment.  tslb_rollout_backward then takes lam (10N, in: dL/dM at the
  * final level, out: dL/dM at the initial level) and accumulates dL/dg into
  * dg_accum (3N, may be NULL), recomputing each segment once from its
- * checkpoint and running tslb_adjoint_step backwards through it; the
- * handle's state is left at an unspecified level.                          */
+ * checkpoint (each level computed straight into the workspace) and running
+ * tslb_adjoint_step backwards through it; the handle's state and level are
+ * left as they were.                                                         */
 size_t tslb_rollout_workspace_bytes(tslb_handle h, int nsteps, int every);
 int tslb_rollout_forward(tslb_handle h, int nsteps, int every, void *ws, size_t ws_bytes, void *stream);
 int tslb_rollout_backward(tslb_handle h, int nsteps, int every, void *ws, size_t ws_bytes, float *lam,

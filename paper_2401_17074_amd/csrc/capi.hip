@@ -93,6 +93,9 @@ int tslb_create(int nx, int ny, int nz, int lattice, float tau, const float forc
     if (lattice != TSLB_D3Q27 && lattice != TSLB_D3Q19 && lattice != TSLB_D2Q9)
         return fail(TSLB_E_UNSUPPORTED, "lattice %d: D3Q27 (27), D3Q19 (19) and D2Q9 (9) are provided", lattice);
     if (nx < 1 || ny < 1 || nz < 1) return fail(TSLB_E_INVALID, "grid dimensions must be >= 1");
+    if ((long long)nx * ny * nz >= TSLB_MAX_NODES)
+        return fail(TSLB_E_INVALID, "grid of %lld nodes: at most %lld nodes (32-bit byte offsets per field)",
+                    (long long)nx * ny * nz, (long long)TSLB_MAX_NODES - 1);
     if (!(tau > 0.5f) || !isfinite(tau)) return fail(TSLB_E_INVALID, "tau must exceed 1/2 (got %g)", (double)tau);
     tslb_bc b;
     memset(&b, 0, sizeof b);
@@ -622,6 +625,8 @@ int tslb_rollout_backward(tslb_handle h, int nsteps, int every, void* ws, size_t
     if (ws_bytes < tslb_rollout_workspace_bytes(h, nsteps, every)) return fail(TSLB_E_INVALID, "workspace too small");
     if (h->p.order != 3 || h->lattice != TSLB_D3Q27)
         return fail(TSLB_E_UNSUPPORTED, "the adjoint differentiates the third-order D3Q27 update only");
+    if (h->storage != TSLB_FP32 || h->has_ghosts)
+        return fail(TSLB_E_UNSUPPORTED, "the adjoint needs FP32 storage and no inlet/outlet ghosts");
     DeviceGuard dg(h->device);
     hipStream_t s = S(stream);
     const size_t sb = tslb_state_bytes(h);
@@ -632,23 +637,26 @@ int tslb_rollout_backward(tslb_handle h, int nsteps, int every, void* ws, size_t
     float* a = lam;      // holds lambda at the current level
     float* b = lam_tmp;
     const int64_t t_end = h->t;
+    // The update writes fluid nodes only and relies on wall nodes holding the
+    // rest state, so before the first recomputation every slot gets a
+    // checkpoint's copy; afterwards the slots hold earlier levels, whose wall
+    // nodes are at rest as well.
+    if ((h->p.geo.lo_solid | h->p.geo.hi_solid) != 0)
+        for (int k = 1; k <= every; ++k)
+            HIP_TRY(hipMemcpyAsync(seg_states + (size_t)k * sb, ck, sb, hipMemcpyDeviceToDevice, s));
     for (int seg = nseg - 1; seg >= 0; --seg) {
         const int s0 = seg * every;
         const int len = (nsteps - s0 < every) ? nsteps - s0 : every;
-        // recompute the segment once from its checkpoint
-        int rc = tslb_load_state(h, ck + (size_t)seg * sb, stream);
-        if (rc) return rc;
-        h->t = t_end - nsteps + s0;
-        rc = tslb_save_state(h, seg_states, stream);
-        if (rc) return rc;
+        // recompute the segment once from its checkpoint, each level straight
+        // into its slot (the handle's own buffers are not touched)
+        HIP_TRY(hipMemcpyAsync(seg_states, ck + (size_t)seg * sb, sb, hipMemcpyDeviceToDevice, s));
         for (int k = 1; k <= len; ++k) {
-            rc = tslb_step(h, 1, stream);
-            if (rc) return rc;
-            rc = tslb_save_state(h, seg_states + (size_t)k * sb, stream);
-            if (rc) return rc;
+            h->t = t_end - nsteps + s0 + k - 1;
+            HIP_TRY(run_update(h, seg_states + (size_t)(k - 1) * sb, seg_states + (size_t)k * sb, s));
         }
+        h->t = t_end;
         for (int k = len - 1; k >= 0; --k) {
-            rc = tslb_adjoint_step(h, seg_states + (size_t)k * sb, seg_states + (size_t)(k + 1) * sb, a, b,
+            const int rc = tslb_adjoint_step(h, seg_states + (size_t)k * sb, seg_states + (size_t)(k + 1) * sb, a, b,
                                    dg_accum, stream);
             if (rc) return rc;
             float* tmp = a;

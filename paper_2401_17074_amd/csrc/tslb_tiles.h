@@ -41,6 +41,14 @@ namespace tile {
 // -1: deferred only in the instantiation with walls, where the wall branch
 // leaves the stores more latency to hide behind (measured: +2 % on the
 // walled channels, -2 % on the wall-free periodic box)
+// 1: with one LDS buffer, a plane's 24 arriving values are read into
+// registers right after the exchange barrier and the second barrier (which
+// frees the buffer for the next plane) follows at once; the gather sums,
+// the stores and the next plane's build then form one barrier-free phase
+// (measured: +1 % on the 512^3 box, +3 % on the jet, neutral on the channel)
+#ifndef TSLB_EARLY_RELEASE
+#define TSLB_EARLY_RELEASE 1
+#endif
 #ifndef TSLB_DEFER_STORE
 #define TSLB_DEFER_STORE -1
 #endif

@@ -190,19 +190,33 @@ __global__ void __launch_bounds__(NTHREADS, TSLB_WAVES_PER_EU) update_tiled_kern
                 load_node<S>(f, col + plane_nodes * (unsigned)plane_index(zp + 2, nz, pz), p, mnext);
         }
         __syncthreads();
-        if (interior) {
-            // gather the populations arriving from this plane, one cz slice at a
-            // time (nine values), and reduce each slice straight into its plane
-            auto gather_slice = [&]<int CZ>(float (&F)[3][3]) {
-                Unroll<0, 9>::run([&]<int K>() {
-                    constexpr int I = 9 * (CZ + 1) + K;
-                    constexpr int X = cx_of(I), Y = cy_of(I);
-                    if constexpr (X == 0 && Y == 0)
-                        F[Y + 1][X + 1] = G[I];
-                    else
-                        F[Y + 1][X + 1] = lds[slot_of(I)][ly - Y][lx - X];
-                });
-            };
+        // gather the populations arriving from this plane, one cz slice at a
+        // time (nine values), and reduce each slice straight into its plane
+        auto gather_slice = [&]<int CZ>(float (&F)[3][3]) {
+            Unroll<0, 9>::run([&]<int K>() {
+                constexpr int I = 9 * (CZ + 1) + K;
+                constexpr int X = cx_of(I), Y = cy_of(I);
+                if constexpr (X == 0 && Y == 0)
+                    F[Y + 1][X + 1] = G[I];
+                else
+                    F[Y + 1][X + 1] = lds[slot_of(I)][ly - Y][lx - X];
+            });
+        };
+        constexpr bool kEarly = TSLB_EARLY_RELEASE && NBUF == 1;
+        if constexpr (kEarly) {
+            float F3[3][3][3];
+            if (interior) {
+                gather_slice.template operator()<-1>(F3[0]);
+                gather_slice.template operator()<0>(F3[1]);
+                gather_slice.template operator()<1>(F3[2]);
+            }
+            __syncthreads();  // the buffer is free for the next plane
+            if (interior) {
+                add_slice<-1>(F3[0], aprev);
+                add_slice<0>(F3[1], acur);
+                add_slice<1, true>(F3[2], anext);
+            }
+        } else if (interior) {
             float F[3][3];
             gather_slice.template operator()<-1>(F);
             add_slice<-1>(F, aprev);
@@ -244,7 +258,7 @@ __global__ void __launch_bounds__(NTHREADS, TSLB_WAVES_PER_EU) update_tiled_kern
 #pragma unroll
             for (int q = 0; q < 10; ++q) mcur[q] = mnext[q];
         }
-        if (NBUF == 1) __syncthreads();
+        if (NBUF == 1 && !kEarly) __syncthreads();
     };
 
     // Rolling roles of the three accumulators, unrolled to their period so

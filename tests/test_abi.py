@@ -51,6 +51,7 @@ def test_struct_layout_matches_header():
     ((8, 8, 8, 27, 0.5), -1),     # tau must exceed 1/2
     ((0, 8, 8, 27, 0.8), -1),     # dims
     ((8, 8, 8, 27, float("nan")), -1),
+    ((1024, 1024, 1024, 27, 0.8), -1),  # 2^30 nodes: beyond 32-bit field offsets
 ])
 def test_create_rejects_invalid_arguments(lib, args, code):
     from paper_2401_17074_amd import _binding as C

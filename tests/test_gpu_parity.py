@@ -158,6 +158,53 @@ def test_channel_full_size_sampled(kernel):
     assert abs(r1[0] - r0[0]) < 1e-6 * r0[0]
 
 
+def test_max_size_periodic_sampled():
+    """The largest grid the 32-bit field offsets allow, 1024 x 1024 x 1023
+    (just under 2^30 nodes, 86 GB of FP32 state), tiled kernel: one step
+    from a seeded random state, checked at sampled nodes against the oracle
+    run on each node's 3x3x3 neighbourhood (on a 3^3 periodic grid the
+    centre node's update reads exactly those 27 nodes), plus FP64
+    conservation of mass and momentum over the whole grid."""
+    import torch
+    case = W.Case("max_periodic", 1024, 1024, 1023, 0.6)
+    nz, ny, nx = case.shape
+    assert case.nodes < 2 ** 30
+    st = W.random_state_device(case.shape, seed=2024)
+    s = gpu_solver(case, kernel=0)
+    s.set_state(st)
+    idx = W.sample_nodes(case, 400, seed=9)
+    x, y, z = idx % nx, (idx // nx) % ny, idx // (nx * ny)
+    d = np.arange(-1, 2)
+    zz = (z[:, None, None, None] + d[None, :, None, None]) % nz
+    yy = (y[:, None, None, None] + d[None, None, :, None]) % ny
+    xx = (x[:, None, None, None] + d[None, None, None, :]) % nx
+    nbr = torch.from_numpy(((zz * ny + yy) * nx + xx).reshape(-1)).cuda()
+    pre = st.view(10, -1)[:, nbr].double().cpu().numpy().reshape(10, idx.size, 3, 3, 3)
+    del st
+    torch.cuda.empty_cache()
+    r0, _ = s.reduce()
+    s.step(1)
+    r1, rc = s.reduce()
+    post = s.get_state()
+    got = post.view(10, -1)[:, torch.from_numpy(idx).cuda()].double().cpu().numpy()
+    del post
+    s.close()
+    torch.cuda.empty_cache()
+    got[0] += 1.0
+    G3 = oracle_grid(W.Case("neighbourhood", 3, 3, 3, case.tau))
+    want = np.empty_like(got)
+    for k in range(idx.size):
+        loc = pre[:, k].copy()
+        loc[0] += 1.0
+        want[:, k] = oracle.update_nodes(G3, loc, np.array([13]))[:, 0]
+    assert rc == 0
+    assert np.abs(got[0] - want[0]).max() < 1e-7
+    assert np.abs(got[1:4] - want[1:4]).max() < 2e-6 * np.abs(want[1:4]).max()
+    assert np.abs(got[4:] - want[4:]).max() < pi_tol(want)
+    assert abs(r1[0] - r0[0]) < 1e-9 * r0[0]
+    assert np.abs(np.asarray(r1[1:4]) - np.asarray(r0[1:4])).max() < 1e-9 * r0[0]
+
+
 @pytest.mark.parametrize("kernel", KERNELS)
 def test_jet_full_size_sampled(kernel):
     """512x256x256 jet (inlet disc, outflow ghosts elsewhere): 10 steps, then

@@ -2,7 +2,8 @@
 
 This module holds no arithmetic of the lattice Boltzmann method: it only
 builds initial moment fields, force fields and case parameters, in float64
-numpy arrays of shape (10, nz, ny, nx) (rho, u_x, u_y, u_z, Pi^neq xx, yy, zz,
+numpy arrays (one generator draws on the GPU, for grids too large for the
+host) of shape (10, nz, ny, nx) (rho, u_x, u_y, u_z, Pi^neq xx, yy, zz,
 xy, xz, yz) or (3, nz, ny, nx) for a body-force field.  Both the HIP path and
 the FP64 oracle consume what it returns; neither is imported here.
 
@@ -212,6 +213,20 @@ def random_state(shape, seed, u_amp=0.03, rho_amp=0.01, pi_amp=1e-3):
     st[0] = 1.0 + rng.uniform(-rho_amp, rho_amp, size=shape)
     st[1:4] = rng.uniform(-u_amp, u_amp, size=(3,) + tuple(shape))
     st[4:10] = rng.uniform(-pi_amp, pi_amp, size=(6,) + tuple(shape))
+    return st
+
+
+def random_state_device(shape, seed, u_amp=0.03, rho_amp=0.01, pi_amp=1e-3):
+    """The same distributions as random_state, drawn on the current GPU with a
+    seeded torch generator, as float32 (rho - 1, u, Pi): for grids whose
+    state is too large to build on the host."""
+    import torch
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(seed)
+    st = torch.empty((10,) + tuple(shape), dtype=torch.float32, device="cuda")
+    st[0].uniform_(-rho_amp, rho_amp, generator=gen)
+    st[1:4].uniform_(-u_amp, u_amp, generator=gen)
+    st[4:10].uniform_(-pi_amp, pi_amp, generator=gen)
     return st
 
 
