@@ -165,9 +165,10 @@ def measure_adjoint(kernel):
             "adjoint_kernel_over_update_kernel": round(k_adj / k_fwd, 3)}
 
 
-def cpu_baseline(case, st64, seconds_budget=15.0):
+def cpu_baseline(case, st64, seconds_budget=12.0):
     """The FP64 oracle as it stands, on the host cores: single-step updates of a
-    contiguous block of z-planes of the same channel state."""
+    contiguous block of z-planes of the same channel state, repeated until
+    about seconds_budget of CPU time has been spent."""
     import numpy as np
     import oracle
     G = oracle.make_grid(case.nx, case.ny, case.nz, case.tau, faces=case.faces, force=case.force)
@@ -182,13 +183,18 @@ def cpu_baseline(case, st64, seconds_budget=15.0):
     nplanes = int(max(1, min(case.nz - 2, seconds_budget / max(dt, 1e-6))))
     idx = np.arange(plane, (1 + nplanes) * plane)
     idx = idx[kinds[idx] == 0]
+    reps = 0
     t0 = time.perf_counter()
-    oracle.update_nodes(G, st64, idx)
-    dt = time.perf_counter() - t0
-    return {"value": round(idx.size / dt / 1e6, 4), "unit": "MLUPS", "cores": oracle.num_threads(),
+    while True:
+        oracle.update_nodes(G, st64, idx)
+        reps += 1
+        dt = time.perf_counter() - t0
+        if dt >= 0.8 * seconds_budget or reps >= 100:
+            break
+    return {"value": round(reps * idx.size / dt / 1e6, 4), "unit": "MLUPS", "cores": oracle.num_threads(),
             "kind": "oracle",
-            "sample": "one FP64 update of %d fluid nodes (%d z-planes) of the %s initial state, %.1f s"
-                      % (idx.size, nplanes, case.name, dt)}
+            "sample": "%d x one FP64 update of %d fluid nodes (%d z-planes) of the %s initial state, %.1f s"
+                      % (reps, idx.size, nplanes, case.name, dt)}
 
 
 def load_traffic(kernel_name, case_name, storage):

@@ -21,36 +21,17 @@ namespace tile {
 #ifndef TSLB_WAVES_PER_EU
 #define TSLB_WAVES_PER_EU 4
 #endif
-#ifndef TSLB_LDS_DOUBLE
-#define TSLB_LDS_DOUBLE 0
-#endif
-#ifndef TSLB_EARLY_PREFETCH
-#define TSLB_EARLY_PREFETCH 0
-#endif
-#ifndef TSLB_PREFETCH_DEPTH
-#define TSLB_PREFETCH_DEPTH 1
-#endif
 // 1 (default): the tiled update adds the bounced-back populations of
 // wall-adjacent nodes itself, from the populations the node has just built;
 // 0: it leaves their raw sums in a side buffer for the wall fix-up launch
 #ifndef TSLB_FUSED_WALLS
 #define TSLB_FUSED_WALLS 1
 #endif
-// 1: a plane's outputs are stored during the next plane's build (after its
-// LDS writes) instead of right after the gather; 0: right after the gather;
-// -1: deferred only in the instantiation with walls, where the wall branch
-// leaves the stores more latency to hide behind (measured: +2 % on the
-// walled channels, -2 % on the wall-free periodic box)
-// 1: with one LDS buffer, a plane's 24 arriving values are read into
-// registers right after the exchange barrier and the second barrier (which
-// frees the buffer for the next plane) follows at once; the gather sums,
-// the stores and the next plane's build then form one barrier-free phase
-// (measured: +1 % on the 512^3 box, +3 % on the jet, neutral on the channel)
-#ifndef TSLB_EARLY_RELEASE
-#define TSLB_EARLY_RELEASE 1
-#endif
-#ifndef TSLB_DEFER_STORE
-#define TSLB_DEFER_STORE -1
+// 1 (default): one resident block per CU walks several tiles (see TileWalk)
+// and loads the next tile's first plane while it finishes the current one;
+// 0: one block per tile
+#ifndef TSLB_PERSISTENT
+#define TSLB_PERSISTENT 1
 #endif
 constexpr int TX = TSLB_TILE_X;              // interior tile width (64: one wave per row)
 constexpr int TY = TSLB_TILE_Y;              // interior rows
@@ -61,11 +42,6 @@ constexpr int NTHREADS = NINT + ((NHALO + 63) / 64) * 64;
 static_assert(NINT % 64 == 0, "interior threads must fill whole wavefronts");
 static_assert(NTHREADS <= 1024, "a block holds at most 1024 threads");
 constexpr int NSLOT = 24;                    // populations with (cx, cy) != (0, 0)
-// With two LDS buffers (alternating planes) one barrier per plane suffices:
-// a thread writes plane p + 1 only after it has gathered plane p, and the
-// barrier after those writes orders every read of plane p before the
-// writes of plane p + 2 into the same buffer.
-constexpr int NBUF = TSLB_LDS_DOUBLE ? 2 : 1;
 
 __host__ __device__ constexpr int slot_of(int I) { return I - (I > 4) - (I > 13) - (I > 22); }
 
@@ -369,7 +345,7 @@ inline int choose_tz(int columns, int nz, int cus) {
 // Blocks of the tiled kernels that one CU holds at once: bounded by LDS
 // (160 KB per CU) and by the waves the register budget allows (4 SIMDs x
 // TSLB_WAVES_PER_EU waves).
-constexpr int kLdsBytes = NBUF * NSLOT * LY * LX * 4;
+constexpr int kLdsBytes = NSLOT * LY * LX * 4;
 constexpr int kBlocksPerCu = (163840 / kLdsBytes) < ((4 * TSLB_WAVES_PER_EU) / (NTHREADS / 64))
                                  ? (163840 / kLdsBytes)
                                  : ((4 * TSLB_WAVES_PER_EU) / (NTHREADS / 64));
@@ -387,6 +363,28 @@ __device__ __forceinline__ int xcd_tile(int b, int nblk) {
 }
 inline unsigned xcd_grid(int nblk) { return (unsigned)((nblk + 7) & ~7); }
 
+// The tiles one block of the update processes.  Block ids are dealt
+// round-robin to the 8 XCDs; each XCD owns a contiguous run of
+// ceil(ntiles / 8) tiles (x fastest, then y, then z) that its gridDim / 8
+// blocks walk with stride gridDim / 8, so the tiles that run together on one
+// XCD are x and y neighbours marching the same planes and the halo columns
+// and rows they read from each other are L2 hits.  With one block per tile
+// (walk_grid with TSLB_PERSISTENT 0) every block takes a single tile.  The
+// grid size must be a multiple of 8.
+struct TileWalk {
+    int hi, stride, start;
+    __device__ TileWalk(int blk, int nblk, int ntiles) {
+        const int per = (ntiles + 7) >> 3;
+        const int lo = (blk & 7) * per;
+        hi = min(lo + per, ntiles);
+        stride = nblk >> 3;
+        start = lo + (blk >> 3);
+    }
+    __device__ int first() const { return start < hi ? start : -1; }
+    __device__ int next(int t) const { return t + stride < hi ? t + stride : -1; }
+};
+
+
 inline int compute_units() {
     static int cus = 0;
     if (cus == 0) {
@@ -397,6 +395,15 @@ inline int compute_units() {
         if (cus <= 0) cus = 256;
     }
     return cus;
+}
+
+// Grid of the tiled update: one block per tile, or at most the blocks that
+// are resident at once (kBlocksPerCu per CU), rounded up to a multiple of 8.
+inline unsigned walk_grid(int ntiles) {
+    const unsigned all = xcd_grid(ntiles);
+    if (!TSLB_PERSISTENT) return all;
+    const unsigned resident = (unsigned)((compute_units() * kBlocksPerCu + 7) & ~7);
+    return all < resident ? all : resident;
 }
 
 

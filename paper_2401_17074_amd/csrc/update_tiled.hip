@@ -17,9 +17,9 @@
 // evaluation over z, then x, then y.  The arriving populations are reduced
 // to moments by the transposed separable sums.
 //
-// Block = TX x TY interior columns plus a one-node halo ring (extra waves);
-// it marches tz planes (plus one halo plane each side), tz chosen per grid
-// at launch.  A plane's emitted
+// Tile = TX x TY interior columns plus a one-node halo ring (extra waves)
+// marching tz planes (plus one halo plane each side), tz chosen per grid at
+// launch; one resident block per CU walks a sequence of tiles.  A plane's emitted
 // populations with (cx, cy) != (0, 0) go through LDS; the three with
 // cx = cy = 0 stay in the thread.  Contributions to the output planes
 // p - 1, p, p + 1 are accumulated in three rolling register sets.
@@ -34,24 +34,15 @@ using namespace tile;
 template <class S, bool WALLS, bool FIELD, int ORDER, int LAT>
 __global__ void __launch_bounds__(NTHREADS, TSLB_WAVES_PER_EU) update_tiled_kernel(const FieldPtrs<typename S::T> f, StepParams p,
                                                                    int tiles_x, int tiles_y, int tiles_z, int TZ) {
-    __shared__ float lds_all[NBUF][NSLOT][LY][LX];
+    __shared__ float lds[NSLOT][LY][LX];
     const Geometry& g = p.geo;
     const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
     const unsigned plane_nodes = (unsigned)nx * (unsigned)ny;
+    const bool pz = (g.periodic & 4) != 0;
 
-    // Tile order: consecutive block ids are dealt round-robin to the 8 XCDs;
-    // give each XCD a contiguous run of tiles, x fastest, then y, then z, so
-    // the tiles that run together on one XCD are x and y neighbours marching
-    // the same planes: the halo columns and rows they read from each other
-    // are then L2 hits instead of HBM reads.
-    const int b = xcd_tile(blockIdx.x, tiles_x * tiles_y * tiles_z);
-    if (b < 0) return;  // padding block (before any barrier)
-    const int tx = b % tiles_x;
-    const int ty = (b / tiles_x) % tiles_y;
-    const int tz = b / (tiles_x * tiles_y);
-    const int x0 = tx * TX, y0 = ty * TY;
-    const int zs = tz * TZ;
-    const int ze = min(zs + TZ, nz);
+    const TileWalk walk(blockIdx.x, gridDim.x, tiles_x * tiles_y * tiles_z);
+    int t = walk.first();
+    if (t < 0) return;  // no tile for this block (before any barrier)
 
     // thread -> LDS column (lx, ly); interior columns first, whole waves
     const int tid = threadIdx.x;
@@ -79,201 +70,175 @@ __global__ void __launch_bounds__(NTHREADS, TSLB_WAVES_PER_EU) update_tiled_kern
             active = false;
         }
     }
-    const int gx = x0 - 1 + lx, gy = y0 - 1 + ly;
-    const int wx = wrap_or_clamp(gx, nx, g.periodic & 1);
-    const int wy = wrap_or_clamp(gy, ny, g.periodic & 2);
-    const unsigned col = (unsigned)wx + (unsigned)nx * (unsigned)wy;
-    const bool pz = (g.periodic & 4) != 0;
-
-    // interior column output properties
-    const bool valid = interior && gx < nx && gy < ny;
-    bool col_fluid = valid;
-    if (valid) {
-        col_fluid &= !((gx == 0) && (((g.lo_solid | g.lo_ghost) & 1)));
-        col_fluid &= !((gx == nx - 1) && (((g.hi_solid | g.hi_ghost) & 1)));
-        col_fluid &= !((gy == 0) && (((g.lo_solid | g.lo_ghost) & 2)));
-        col_fluid &= !((gy == ny - 1) && (((g.hi_solid | g.hi_ghost) & 2)));
-    }
-    const int wf = (WALLS && interior) ? wall_flags(g, gx, gy) : 0;
-    // Wall nodes emit nothing: their stored moments are the zero deviation
-    // (rest state) and their forcing is switched off here, so every
-    // population they would publish is exactly 0 and the gather needs no
-    // masking.  Fluid neighbours get the bounced-back populations instead.
-    bool col_solid = false;
-    if (WALLS) {
-        col_solid |= (wx == 0 && (g.lo_solid & 1)) || (wx == nx - 1 && (g.hi_solid & 1));
-        col_solid |= (wy == 0 && (g.lo_solid & 2)) || (wy == ny - 1 && (g.hi_solid & 2));
-    }
     const bool zlo_wall = (g.lo_solid & 4) != 0, zhi_wall = (g.hi_solid & 4) != 0;
     const bool zlo_out = ((g.lo_solid | g.lo_ghost) & 4) != 0, zhi_out = ((g.hi_solid | g.hi_ghost) & 4) != 0;
 
-    const float gon = col_solid ? 0.0f : 1.0f;
-    float gacc[3] = {gon * p.force[0], gon * p.force[1], gon * p.force[2]};
-
-    float mcur[10];
-    if (active) load_node<S>(f, col + plane_nodes * (unsigned)plane_index(zs - 1, nz, pz), p, mcur);
-    // With a prefetch depth of 2 the moments of plane zp + 1 are already in
-    // registers (m_ahead) while plane zp is processed, and the loads of plane
-    // zp + 2 are issued: twice the bytes in flight per thread.
-    float m_ahead[10];
-    if (TSLB_PREFETCH_DEPTH == 2 && active)
-        load_node<S>(f, col + plane_nodes * (unsigned)plane_index(zs, nz, pz), p, m_ahead);
-
-    // Finalised moments of one output node, stored at byte offset pend_on.
-    constexpr bool kDefer = TSLB_DEFER_STORE < 0 ? WALLS : TSLB_DEFER_STORE != 0;
-    float pend[10];
-    unsigned pend_on = 0;
-    bool pend_valid = false;
-    auto store_pending = [&]() {
-        if (!pend_valid) return;
-        store_out(at(f.out[0], pend_on), S::store(pend[0], p.scale[0]));
-#pragma unroll
-        for (int q = 1; q < 4; ++q) store_out(at(f.out[q], pend_on), S::store(pend[q], p.scale[1]));
-#pragma unroll
-        for (int q = 4; q < 10; ++q) store_out(at(f.out[q], pend_on), S::store(pend[q], p.scale[2]));
-        pend_valid = false;
+    // this thread's column in tile t and the tile's z range
+    struct Column {
+        int gx, gy;    // grid coordinates (one outside the grid for halo columns)
+        int wx, wy;    // wrapped (periodic) or clamped coordinates
+        unsigned col;  // wx + nx wy
+        int zs, ze;    // output planes [zs, ze)
+    };
+    auto column = [&](int tile) {
+        Column c;
+        const int tx = tile % tiles_x, ty = (tile / tiles_x) % tiles_y, tz = tile / (tiles_x * tiles_y);
+        c.gx = tx * TX - 1 + lx;
+        c.gy = ty * TY - 1 + ly;
+        c.wx = wrap_or_clamp(c.gx, nx, g.periodic & 1);
+        c.wy = wrap_or_clamp(c.gy, ny, g.periodic & 2);
+        c.col = (unsigned)c.wx + (unsigned)nx * (unsigned)c.wy;
+        c.zs = tz * TZ;
+        c.ze = min(c.zs + TZ, nz);
+        return c;
     };
 
-    // One plane zp with moments mcur: prefetch the next plane into mnext,
-    // build and publish this plane's populations, add what arrives from it
-    // to the output planes zp - 1 (aprev), zp (acur) and zp + 1 (anext, which
-    // starts here), then store the completed plane zp - 1.
-    auto plane = [&](int zp, MomentSums& aprev, MomentSums& acur, MomentSums& anext) {
-        const unsigned node = col + plane_nodes * (unsigned)plane_index(zp, nz, pz);
-        float(&lds)[NSLOT][LY][LX] = lds_all[NBUF == 2 ? ((zp - zs + 1) & 1) : 0];
-        float mnext[10];
-        const bool have_next = zp + 1 <= ze;
-        if (TSLB_PREFETCH_DEPTH == 1 && TSLB_EARLY_PREFETCH && active && have_next)
-            load_node<S>(f, col + plane_nodes * (unsigned)plane_index(zp + 1, nz, pz), p, mnext);
+    Column c = column(t);
+    float mcur[10];  // moments of the plane being built
+    if (active) load_node<S>(f, c.col + plane_nodes * (unsigned)plane_index(c.zs - 1, nz, pz), p, mcur);
 
-        float G[27];
-        if (active) {
-            if (FIELD) {
+    for (;;) {
+        // the block's next tile: its first plane is loaded while the last
+        // plane of this one is exchanged and gathered
+        const int tn = walk.next(t);
+        const Column cn = column(tn >= 0 ? tn : t);
+        const int gx = c.gx, gy = c.gy, zs = c.zs, ze = c.ze;
+
+        // interior column output properties
+        const bool valid = interior && gx < nx && gy < ny;
+        bool col_fluid = valid;
+        if (valid) {
+            col_fluid &= !((gx == 0) && (((g.lo_solid | g.lo_ghost) & 1)));
+            col_fluid &= !((gx == nx - 1) && (((g.hi_solid | g.hi_ghost) & 1)));
+            col_fluid &= !((gy == 0) && (((g.lo_solid | g.lo_ghost) & 2)));
+            col_fluid &= !((gy == ny - 1) && (((g.hi_solid | g.hi_ghost) & 2)));
+        }
+        const int wf = (WALLS && interior) ? wall_flags(g, gx, gy) : 0;
+        // Wall nodes emit nothing: their stored moments are the zero deviation
+        // (rest state) and their forcing is switched off here, so every
+        // population they would publish is exactly 0 and the gather needs no
+        // masking.  Fluid neighbours get the bounced-back populations instead.
+        bool col_solid = false;
+        if (WALLS) {
+            col_solid |= (c.wx == 0 && (g.lo_solid & 1)) || (c.wx == nx - 1 && (g.hi_solid & 1));
+            col_solid |= (c.wy == 0 && (g.lo_solid & 2)) || (c.wy == ny - 1 && (g.hi_solid & 2));
+        }
+        const float gon = col_solid ? 0.0f : 1.0f;
+        float gacc[3] = {gon * p.force[0], gon * p.force[1], gon * p.force[2]};
+
+        // One plane zp with moments mcur: build and publish its populations,
+        // load the next plane (or the next tile's first plane) into mcur, add
+        // what arrives from plane zp to the output planes zp - 1 (aprev), zp
+        // (acur) and zp + 1 (anext, which starts here), then store the
+        // completed plane zp - 1.
+        auto plane = [&](int zp, MomentSums& aprev, MomentSums& acur, MomentSums& anext) {
+            const unsigned node = c.col + plane_nodes * (unsigned)plane_index(zp, nz, pz);
+            float G[27];
+            if (active) {
+                if (FIELD) {
 #pragma unroll
-                for (int a = 0; a < 3; ++a) gacc[a] = gon * ld_at(f.g[a], node * 4u);
+                    for (int a = 0; a < 3; ++a) gacc[a] = gon * ld_at(f.g[a], node * 4u);
+                }
+                float A[NK];
+                const float omo = omo_at(p, plane_index(zp, nz, pz));
+                if (WALLS) {
+                    // a wall plane (z walls) emits nothing either
+                    const bool plane_solid = (zlo_wall && zp == 0) || (zhi_wall && zp == nz - 1);
+                    const float gp = plane_solid ? 0.0f : 1.0f;
+                    const float gz[3] = {gp * gacc[0], gp * gacc[1], gp * gacc[2]};
+                    coefficients<ORDER, LAT>(mcur, gz, omo, A);
+                } else {
+                    coefficients<ORDER, LAT>(mcur, gacc, omo, A);
+                }
+                populations<LAT>(A, G);
+                if (WALLS && TSLB_FUSED_WALLS && interior && col_fluid) {
+                    // half-way bounce-back in place: a fluid node next to a wall
+                    // receives its own population along -c for every c whose
+                    // upstream node is solid; it holds those values right here
+                    const bool zlo_adj = zlo_wall && zp == 1, zhi_adj = zhi_wall && zp == nz - 2;
+                    if (wf != 0 || zlo_adj || zhi_adj) {
+                        Unroll<0, 27>::run([&]<int I>() {
+                            if (upstream_solid<I>(wf, zlo_adj, zhi_adj)) acur.template add<I>(G[26 - I]);
+                        });
+                    }
+                }
+                Unroll<0, 27>::run([&]<int I>() {
+                    if constexpr (cx_of(I) != 0 || cy_of(I) != 0) lds[slot_of(I)][ly][lx] = G[I];
+                });
+                // mcur is dead once the coefficients are formed: the next
+                // plane's moments go straight into it and are in flight across
+                // the exchange and the gather
+                if (zp + 1 <= ze)
+                    load_node<S>(f, c.col + plane_nodes * (unsigned)plane_index(zp + 1, nz, pz), p, mcur);
+                else if (tn >= 0)
+                    load_node<S>(f, cn.col + plane_nodes * (unsigned)plane_index(cn.zs - 1, nz, pz), p, mcur);
             }
-            float A[NK];
-            const float omo = omo_at(p, plane_index(zp, nz, pz));
-            if (WALLS) {
-                // a wall plane (z walls) emits nothing either
-                const bool plane_solid = (zlo_wall && zp == 0) || (zhi_wall && zp == nz - 1);
-                const float gp = plane_solid ? 0.0f : 1.0f;
-                const float gz[3] = {gp * gacc[0], gp * gacc[1], gp * gacc[2]};
-                coefficients<ORDER, LAT>(mcur, gz, omo, A);
-            } else {
-                coefficients<ORDER, LAT>(mcur, gacc, omo, A);
+            __syncthreads();
+            // the 24 values arriving through LDS go to registers at once, so
+            // the buffer is free again after the second barrier and the gather
+            // sums, the stores and the next plane's build form one
+            // barrier-free phase
+            float F[3][3][3];  // [cz + 1][cy + 1][cx + 1]
+            if (interior) {
+                Unroll<0, 27>::run([&]<int I>() {
+                    constexpr int X = cx_of(I), Y = cy_of(I), Z = cz_of(I);
+                    if constexpr (X == 0 && Y == 0)
+                        F[Z + 1][1][1] = G[I];
+                    else
+                        F[Z + 1][Y + 1][X + 1] = lds[slot_of(I)][ly - Y][lx - X];
+                });
             }
-            populations<LAT>(A, G);
-            if (WALLS && TSLB_FUSED_WALLS && interior && col_fluid) {
-                // half-way bounce-back in place: a fluid node next to a wall
-                // receives its own population along -c for every c whose
-                // upstream node is solid; it holds those values right here
-                const bool zlo_adj = zlo_wall && zp == 1, zhi_adj = zhi_wall && zp == nz - 2;
-                if (wf != 0 || zlo_adj || zhi_adj) {
-                    Unroll<0, 27>::run([&]<int I>() {
-                        if (upstream_solid<I>(wf, zlo_adj, zhi_adj)) acur.template add<I>(G[26 - I]);
-                    });
+            __syncthreads();
+            if (interior) {
+                add_slice<-1>(F[0], aprev);
+                add_slice<0>(F[1], acur);
+                add_slice<1, true>(F[2], anext);
+            }
+            const int zo = zp - 1;
+            if (interior && zo >= zs && zo < ze) {
+                const bool fl = col_fluid && !(zo == 0 && zlo_out) && !(zo == nz - 1 && zhi_out);
+                const bool near_wall =
+                    WALLS && !TSLB_FUSED_WALLS && (wf != 0 || (zlo_wall && zo == 1) || (zhi_wall && zo == nz - 2));
+                if (fl && near_wall) {
+                    // next to a wall: the bounced-back populations are still
+                    // missing; leave the raw sums for the fix-up pass
+                    const int cc[3] = {gx, gy, zo};
+                    const int fw = first_wall_face(g, cc);
+                    float* side = p.wall_side + 10 * (p.wall_off[fw] + wall_layer_index(g, fw, cc));
+                    side[0] = aprev.d;
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) side[1 + a] = aprev.j[a];
+#pragma unroll
+                    for (int k = 0; k < 6; ++k) side[4 + k] = aprev.s[k];
+                } else if (fl) {
+                    float out[10];
+                    finalize<LAT == 19 ? 36 : 216>(aprev, out);
+                    const unsigned on = (c.col + plane_nodes * (unsigned)zo) * (unsigned)sizeof(typename S::T);
+                    store_out(at(f.out[0], on), S::store(out[0], p.scale[0]));
+#pragma unroll
+                    for (int q = 1; q < 4; ++q) store_out(at(f.out[q], on), S::store(out[q], p.scale[1]));
+#pragma unroll
+                    for (int q = 4; q < 10; ++q) store_out(at(f.out[q], on), S::store(out[q], p.scale[2]));
                 }
             }
-            Unroll<0, 27>::run([&]<int I>() {
-                if constexpr (cx_of(I) != 0 || cy_of(I) != 0) lds[slot_of(I)][ly][lx] = G[I];
-            });
-            // the previous plane's outputs go out while this plane is built
-            if (kDefer) store_pending();
-            // prefetch the next plane once this plane's moments are consumed;
-            // the loads are in flight across the exchange and the gather
-            // (mcur is dead once the coefficients are formed, so the next
-            // plane's moments go straight into it: no register copies)
-            if (TSLB_PREFETCH_DEPTH == 1 && !TSLB_EARLY_PREFETCH && have_next)
-                load_node<S>(f, col + plane_nodes * (unsigned)plane_index(zp + 1, nz, pz), p, mcur);
-            if (TSLB_PREFETCH_DEPTH == 2 && zp + 2 <= ze)
-                load_node<S>(f, col + plane_nodes * (unsigned)plane_index(zp + 2, nz, pz), p, mnext);
-        }
-        __syncthreads();
-        // gather the populations arriving from this plane, one cz slice at a
-        // time (nine values), and reduce each slice straight into its plane
-        auto gather_slice = [&]<int CZ>(float (&F)[3][3]) {
-            Unroll<0, 9>::run([&]<int K>() {
-                constexpr int I = 9 * (CZ + 1) + K;
-                constexpr int X = cx_of(I), Y = cy_of(I);
-                if constexpr (X == 0 && Y == 0)
-                    F[Y + 1][X + 1] = G[I];
-                else
-                    F[Y + 1][X + 1] = lds[slot_of(I)][ly - Y][lx - X];
-            });
         };
-        constexpr bool kEarly = TSLB_EARLY_RELEASE && NBUF == 1;
-        if constexpr (kEarly) {
-            float F3[3][3][3];
-            if (interior) {
-                gather_slice.template operator()<-1>(F3[0]);
-                gather_slice.template operator()<0>(F3[1]);
-                gather_slice.template operator()<1>(F3[2]);
-            }
-            __syncthreads();  // the buffer is free for the next plane
-            if (interior) {
-                add_slice<-1>(F3[0], aprev);
-                add_slice<0>(F3[1], acur);
-                add_slice<1, true>(F3[2], anext);
-            }
-        } else if (interior) {
-            float F[3][3];
-            gather_slice.template operator()<-1>(F);
-            add_slice<-1>(F, aprev);
-            gather_slice.template operator()<0>(F);
-            add_slice<0>(F, acur);
-            gather_slice.template operator()<1>(F);
-            add_slice<1, true>(F, anext);
-        }
-        const int zo = zp - 1;
-        if (interior && zo >= zs && zo < ze) {
-            const bool fl = col_fluid && !(zo == 0 && zlo_out) && !(zo == nz - 1 && zhi_out);
-            const bool near_wall =
-                WALLS && !TSLB_FUSED_WALLS && (wf != 0 || (zlo_wall && zo == 1) || (zhi_wall && zo == nz - 2));
-            if (fl && near_wall) {
-                // next to a wall: the bounced-back populations are still missing;
-                // leave the raw sums for the fix-up pass
-                const int c[3] = {gx, gy, zo};
-                const int fw = first_wall_face(g, c);
-                float* side = p.wall_side + 10 * (p.wall_off[fw] + wall_layer_index(g, fw, c));
-                side[0] = aprev.d;
-#pragma unroll
-                for (int a = 0; a < 3; ++a) side[1 + a] = aprev.j[a];
-#pragma unroll
-                for (int k = 0; k < 6; ++k) side[4 + k] = aprev.s[k];
-            } else if (fl) {
-                finalize<LAT == 19 ? 36 : 216>(aprev, pend);
-                pend_on = (col + plane_nodes * (unsigned)zo) * (unsigned)sizeof(typename S::T);
-                pend_valid = true;
-                if (!kDefer) store_pending();
-            }
-        }
-        if (TSLB_PREFETCH_DEPTH == 2) {
-#pragma unroll
-            for (int q = 0; q < 10; ++q) {
-                mcur[q] = m_ahead[q];
-                m_ahead[q] = mnext[q];
-            }
-        } else if (TSLB_EARLY_PREFETCH && have_next) {
-#pragma unroll
-            for (int q = 0; q < 10; ++q) mcur[q] = mnext[q];
-        }
-        if (NBUF == 1 && !kEarly) __syncthreads();
-    };
 
-    // Rolling roles of the three accumulators, unrolled to their period so
-    // every role is a fixed register set.
-    MomentSums a0, a1, a2;
-    a0.zero();
-    a1.zero();
-    for (int zp = zs - 1; zp <= ze; zp += 3) {
-        plane(zp, a0, a1, a2);
-        if (zp + 1 > ze) break;
-        plane(zp + 1, a1, a2, a0);
-        if (zp + 2 > ze) break;
-        plane(zp + 2, a2, a0, a1);
+        // Rolling roles of the three accumulators, unrolled to their period so
+        // every role is a fixed register set.
+        MomentSums a0, a1, a2;
+        a0.zero();
+        a1.zero();
+        for (int zp = zs - 1; zp <= ze; zp += 3) {
+            plane(zp, a0, a1, a2);
+            if (zp + 1 > ze) break;
+            plane(zp + 1, a1, a2, a0);
+            if (zp + 2 > ze) break;
+            plane(zp + 2, a2, a0, a1);
+        }
+        if (tn < 0) break;
+        t = tn;
+        c = cn;
     }
-    store_pending();
 }
 
 // Completes the fluid nodes next to a wall after the tiled update: adds the
@@ -346,8 +311,8 @@ hipError_t launch_t(const void* in, void* out, const StepParams& p, hipStream_t 
     const unsigned nblk = (unsigned)tiles_x * tiles_y * tiles_z;
     if (p.geo.N >= (1LL << 30)) return hipErrorInvalidValue;  // 32-bit node offsets
     const FieldPtrs<typename S::T> f = field_ptrs<S>(in, out, p);
-    hipLaunchKernelGGL((update_tiled_kernel<S, WALLS, FIELD, ORDER, LAT>), dim3(xcd_grid(nblk)), dim3(NTHREADS), 0, s, f, p, tiles_x,
-                       tiles_y, tiles_z, TZ);
+    hipLaunchKernelGGL((update_tiled_kernel<S, WALLS, FIELD, ORDER, LAT>), dim3(walk_grid(nblk)), dim3(NTHREADS), 0, s, f,
+                       p, tiles_x, tiles_y, tiles_z, TZ);
     return hipGetLastError();
 }
 
