@@ -7,17 +7,6 @@ namespace tslb {
 namespace {
 
 // ---------------------------------------------------------------- ghosts
-// SplitMix64 output k of the stream seeded with `seed` (Steele, Lea and
-// Flood, 2014): mix(seed + k * golden gamma).
-__device__ __forceinline__ uint64_t splitmix64(uint64_t seed, uint64_t k) {
-    uint64_t z = seed + k * 0x9e3779b97f4a7c15ull;
-    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
-    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
-    return z ^ (z >> 31);
-}
-
-__device__ __forceinline__ int face_layer(const Geometry& g, int f) { return (f & 1) ? g.n[f >> 1] - 1 : 0; }
-
 // Threads enumerate the six face layers one after the other; a node shared
 // by several ghost faces is written once (by its lowest ghost face).  Each
 // ghost node takes the ten stored values of its interior neighbour
@@ -56,30 +45,9 @@ __global__ void ghost_fill_kernel(typename S::T* __restrict__ st, StepParams p, 
     const long long nf = cf[0] + (long long)g.n[0] * (cf[1] + (long long)g.n[1] * cf[2]);
 #pragma unroll
     for (int k = 0; k < 10; ++k) st[k * g.N + n] = st[k * g.N + nf];
-    for (int f3 = 0; f3 < 6; ++f3) {
-        if (q.face_kind[f3] != kInlet) continue;
-        const int e = f3 >> 1;
-        if (c[e] != face_layer(g, f3)) continue;
-        const int e1 = e == 0 ? 1 : 0, e2 = e == 2 ? 1 : 2;
-        const float r1 = (float)c[e1] - q.center[0], r2 = (float)c[e2] - q.center[1];
-        if (r1 * r1 + r2 * r2 > q.radius2) continue;
-        const uint64_t tn = (uint64_t)t * (uint64_t)g.N + (uint64_t)n;
-        for (int a = 0; a < p.dims; ++a) {
-            float xi;
-            if (q.noise_kind == 1) {
-                // Box-Muller: sqrt(-2 ln v1) cos(2 pi v2), v1 in (0, 1], v2 in [0, 1)
-                const uint64_t k = 1ull + 6ull * tn + 2ull * (uint64_t)a;
-                const float v1 = (float)((splitmix64(q.seed, k) >> 40) + 1) * 0x1.0p-24f;
-                const float v2 = (float)(splitmix64(q.seed, k + 1) >> 40) * 0x1.0p-24f;
-                xi = sqrtf(-2.0f * logf(v1)) * cospif(2.0f * v2);
-            } else {
-                const uint64_t h = splitmix64(q.seed, 1ull + 3ull * tn + (uint64_t)a);
-                xi = (float)(h >> 40) * 0x1.0p-24f * 2.0f - 1.0f;
-            }
-            st[(1 + a) * g.N + n] = S::store(fmaf(q.amp, xi, q.u[a]), p.scale[1]);
-        }
-        break;
-    }
+    float u[3];
+    if (inlet_velocity(g, q, p.dims, t, n, c, u))
+        for (int a = 0; a < p.dims; ++a) st[(1 + a) * g.N + n] = S::store(u[a], p.scale[1]);
 }
 
 // ---------------------------------------------------------------- pack/unpack

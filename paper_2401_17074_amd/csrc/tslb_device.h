@@ -99,17 +99,15 @@ struct StoreF16 {
 };
 
 // bfloat16 kept as raw 16-bit patterns: the upper half of a binary32 after
-// round-to-nearest-even on the dropped 16 bits (NaN stays NaN).
+// round-to-nearest-even on the dropped 16 bits (NaN stays NaN), which is
+// gfx950's own float-to-bfloat16 conversion (one instruction).
 struct StoreBF16 {
     using T = uint16_t;
     __device__ __forceinline__ static float load(T v, float inv_scale) {
         return __uint_as_float(((uint32_t)v) << 16) * inv_scale;
     }
     __device__ __forceinline__ static T store(float v, float scale) {
-        uint32_t b = __float_as_uint(v * scale);
-        if ((b & 0x7f800000u) == 0x7f800000u && (b & 0x007fffffu)) return (T)((b >> 16) | 0x40u);
-        b += 0x7fffu + ((b >> 16) & 1u);
-        return (T)(b >> 16);
+        return __builtin_bit_cast(T, static_cast<__bf16>(v * scale));
     }
 };
 
