@@ -145,7 +145,13 @@ __global__ void __launch_bounds__(kD2Block) update_d2q9_kernel(const Fields2<typ
     const Geometry& g = p.geo;
     const int nx = g.n[0], ny = g.n[1];
     const int lane = threadIdx.x & 63;
-    const int item = blockIdx.x * (kD2Block / 64) + (threadIdx.x >> 6);
+    // Block ids are dealt round-robin to the 8 XCDs (the grid is a multiple
+    // of 8 blocks); each XCD takes a contiguous run of blocks, so the strips
+    // that march side by side share an L2 and the halo columns the edge
+    // lanes read are mostly hits.
+    const int per = (int)(gridDim.x >> 3);
+    const int vb = (int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3);
+    const int item = vb * (kD2Block / 64) + (int)(threadIdx.x >> 6);
     if (item >= strips * segments) return;  // whole wavefronts leave together
     const int strip = item % strips, seg = item / strips;
     const int y0 = seg * seg_rows, y1 = min(y0 + seg_rows, ny);
@@ -281,7 +287,8 @@ hipError_t launch_o(const void* in, void* out, const StepParams& p, int strips, 
                     hipStream_t s) {
     using T = typename S::T;
     const int waves = strips * segments;
-    const unsigned grid = (unsigned)((waves + kD2Block / 64 - 1) / (kD2Block / 64));
+    const unsigned blocks = (unsigned)((waves + kD2Block / 64 - 1) / (kD2Block / 64));
+    const unsigned grid = (blocks + 7u) & ~7u;  // a multiple of 8: whole runs per XCD
     const size_t N = (size_t)p.geo.N;
     Fields2<T> f;
     const int field[6] = {0, 1, 2, 4, 5, 7};
