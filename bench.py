@@ -165,6 +165,37 @@ def measure_adjoint(kernel):
             "adjoint_kernel_over_update_kernel": round(k_adj / k_fwd, 3)}
 
 
+def copy_rate_gbs(mib=1024, reps=20):
+    """Bytes moved per second (read + write) by the runtime's device-to-device
+    copy of `mib` MiB: the practical ceiling of a read+write stream."""
+    import torch
+    n = mib * (1 << 20) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    rate = 2.0 * n * 4 * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del a, b
+    torch.cuda.empty_cache()
+    return rate
+
+
+def fluid_nodes(case):
+    """Nodes that are neither wall nor ghost (x fastest, product of the
+    per-axis counts)."""
+    count = 1
+    for d, n in enumerate((case.nx, case.ny, case.nz)):
+        lo, hi = case.faces[2 * d], case.faces[2 * d + 1]
+        count *= n - (lo in (1, 2, 3)) - (hi in (1, 2, 3))
+    return count
+
+
 def cpu_baseline(case, st64, seconds_budget=12.0):
     """The FP64 oracle as it stands, on the host cores: single-step updates of a
     contiguous block of z-planes of the same channel state, repeated until
@@ -393,6 +424,7 @@ def main():
     _, rc = s.reduce(check=False)
     s.close()
     mlups = case.nodes * args.steps / (ms * 1e-3) / 1e6
+    copy_gbs = copy_rate_gbs()
     kname = "update_d2q9" if case.lattice == 9 else ("update_tiled", "update_direct", "push")[args.kernel]
     per_launch_s = kms * 1e-3 / n_timed
     algo = algorithmic_bytes(case, 0)
@@ -413,11 +445,13 @@ def main():
         "config": {"workload": case.name, "nodes": case.nodes, "lattice": {9: "D2Q9", 19: "D3Q19"}.get(case.lattice, "D3Q27"),
                    "tau": case.tau,
                    "storage": "fp32", "faces": list(case.faces), "kernel": kname, "stable": rc == 0},
+        "fluid_mlups": round(fluid_nodes(case) * args.steps / (ms * 1e-3) / 1e6, 1),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": load_traffic(kname, case.name, 0),
                      "algorithmic_bytes_per_launch": algo, "avg_launch_ms": round(per_launch_s * 1e3, 5),
-                     "kernel": kname, "aux_ms_per_step": round(aux_ms / n_timed, 5)},
+                     "kernel": kname, "aux_ms_per_step": round(aux_ms / n_timed, 5),
+                     "copy_gbs": round(copy_gbs, 1), "frac_of_copy": round(achieved / copy_gbs, 4)},
         "wall_s": round(wall, 3),
     }
     if not args.quick:
