@@ -68,7 +68,7 @@ def test_checkpointed_rollout_gradient_matches_oracle(kernel):
     L = TslbRollout.apply(gt, ut, s, case.steps, case.extra["ckpt"])
     L.backward()
     s.close()
-    assert float(L) == pytest.approx(L_or, rel=1e-5)
+    assert float(L.detach()) == pytest.approx(L_or, rel=1e-5)
     assert _rel(gt.grad.double().cpu().numpy(), dg_or) < 1e-4
     assert _rel(ut.grad.double().cpu().numpy(), lam0_or[1:4]) < 1e-4
 
@@ -160,7 +160,7 @@ def test_wall_shear_objective_rollout_matches_oracle(kernel):
     L = TslbRollout.apply(gt, ut, s, 20, 6, C.TSLB_OBJ_WALL_SHEAR)
     L.backward()
     s.close()
-    assert float(L) == pytest.approx(L_or, rel=1e-4)
+    assert float(L.detach()) == pytest.approx(L_or, rel=1e-4)
     assert _rel(gt.grad.double().cpu().numpy(), dg_or) < 1e-4
     fl = kinds == 0
     assert _rel(ut.grad.double().cpu().numpy()[:, fl], lam0_or[1:4][:, fl]) < 1e-4
