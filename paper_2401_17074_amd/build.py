@@ -14,8 +14,9 @@ FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++20", "-fPIC", "-Wall",
 
 
 def build(verbose=False, defines=()):
-    """Compile and link libtslb.so.  `defines` (e.g. ("TSLB_TILE_Z=64",)) are
-    build-time tuning overrides of the tiled kernel's tile shape."""
+    """Compile and link libtslb.so (all sources in parallel).  `defines`
+    (e.g. ("TSLB_TILE_Y=10", "TSLB_PERSISTENT=0")) are build-time tuning
+    overrides of the tiled kernels."""
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
     obj_dir = os.path.join(ROOT, "_build")
     os.makedirs(obj_dir, exist_ok=True)
