@@ -324,13 +324,13 @@ FieldPtrs<typename S::T> field_ptrs(const void* in, void* out, const StepParams&
 }
 
 // Planes per block: every block costs about (tz + 2) plane-steps and the
-// blocks run in rounds of one per CU, so pick the tz in [4, 64] that
+// blocks run in rounds of one per CU, so pick the tz in [1, 64] that
 // minimises rounds * (tz + 2) (fewer halo planes vs. a ragged last round;
 // small grids get short z-extents so that they still fill the chip).
 inline int choose_tz(int columns, int nz, int cus) {
     int best = 32;
     long long best_cost = -1;
-    for (int tz = 4; tz <= 64; ++tz) {
+    for (int tz = 1; tz <= 64; ++tz) {
         const long long blocks = (long long)columns * ((nz + tz - 1) / tz);
         const long long rounds = (blocks + cus - 1) / cus;
         const long long cost = rounds * (tz + 2);
