@@ -10,7 +10,6 @@ from helpers import from_device_state, gpu_solver, to_device_state
 
 pytestmark = pytest.mark.gpu
 CS2 = 1.0 / 3.0
-KERNELS = [0, 1, 2]
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -21,14 +20,20 @@ def _gpu():
     torch.cuda.set_device(0)
 
 
-@pytest.mark.parametrize("kernel", KERNELS)
+# (kernel variant, lattice): the three D3Q27 variants, D3Q19 and D2Q9
+VARIANTS = [(0, 27), (1, 27), (2, 27), (0, 19), (0, 9)]
+
+
+@pytest.mark.parametrize("kernel,lattice", VARIANTS)
 @pytest.mark.parametrize("tau", [0.8, 1.0])
-def test_poiseuille_steady_state(kernel, tau):
+def test_poiseuille_steady_state(kernel, lattice, tau):
     """Forced flow between the walls y = 1/2 and y = ny - 3/2 from rest to
     its steady state: u(y) = g/(2 nu) [(y - 1/2)(ny - 3/2 - y) - 1/4] + g/2
-    and Pi_xy = -cs2 tau du/dy at the bulk nodes."""
-    nx, ny, nz, g = 64, 18, 4, 1e-6
-    case = W.Case("poiseuille", nx, ny, nz, tau, faces=(0, 0, 1, 1, 0, 0), force=(g, 0.0, 0.0))
+    and Pi_xy = -cs2 tau du/dy at the bulk nodes (the same profile on the
+    three lattices, whose y-marginal is the same three-point set)."""
+    nx, ny, g = 64, 18, 1e-6
+    nz = 1 if lattice == 9 else 4
+    case = W.Case("poiseuille", nx, ny, nz, tau, faces=(0, 0, 1, 1, 0, 0), force=(g, 0.0, 0.0), lattice=lattice)
     nu = CS2 * (float(np.float32(tau)) - 0.5)
     # slowest mode decays as exp(-nu (pi / (ny - 2))^2 t): 5000 steps leave < 1e-8 of it
     s = gpu_solver(case, kernel=kernel)
@@ -46,13 +51,15 @@ def test_poiseuille_steady_state(kernel, tau):
     assert np.abs(pxy + CS2 * float(np.float32(tau)) * dudy).max() < 1e-3 * np.abs(pxy).max()
 
 
-@pytest.mark.parametrize("kernel", KERNELS)
+@pytest.mark.parametrize("kernel,lattice", VARIANTS)
 @pytest.mark.parametrize("order", [3, 2])
-def test_shear_wave_decay(kernel, order):
+def test_shear_wave_decay(kernel, lattice, order):
     """u_x = A sin(k y) with its eigen-stress Pi_xy = s A cos(k y) decays by
     the dominant eigenvalue of the one-step map per step (the linear mode
-    reaches no third-order term, so both orders share it)."""
-    nx, ny, nz, tau, A, steps = 64, 64, 4, 0.8, 1e-3, 50
+    reaches no third-order term, so both orders share it, and the three
+    lattices share the map)."""
+    nx, ny, tau, A, steps = 64, 64, 0.8, 1e-3, 50
+    nz = 1 if lattice == 9 else 4
     tau32 = float(np.float32(tau))
     om = 1.0 / tau32
     k = 2 * np.pi / ny
@@ -60,7 +67,7 @@ def test_shear_wave_decay(kernel, order):
     D = (1 - om) * (1 + 2 * np.cos(k)) / 3
     lam = (T + np.sqrt(T * T - 4 * D)) / 2
     sc = -(np.sin(k) / 3) / (lam - (1 - om) * np.cos(k))
-    case = W.Case("shear", nx, ny, nz, tau, order=order)
+    case = W.Case("shear", nx, ny, nz, tau, order=order, lattice=lattice)
     st0 = W.rest_state(case.shape)
     yy = np.arange(ny)[None, :, None]
     st0[1] = A * np.sin(k * yy) + 0 * st0[1]

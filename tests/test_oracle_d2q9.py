@@ -223,3 +223,16 @@ def test_marginal_of_a_z_invariant_d3q27_step(oracle, faces, order):
     kinds = oracle.node_kinds(G9)
     xy = [0, 1, 2, 4, 5, 7]
     assert np.abs((a[xy] - b[xy])[:, kinds == 0]).max() < 1e-15
+
+
+@pytest.mark.parametrize("tau", [0.8, 1.0])
+def test_poiseuille_between_halfway_walls(oracle, tau):
+    """The D3Q27 steady Poiseuille profile (its y-marginal weights are the
+    same): u(y) = g/(2 nu) [(y - 1/2)(ny - 3/2 - y) - 1/4] + g/2."""
+    ny, g = 12, 1e-6
+    G = oracle.make_grid(1, ny, 1, tau, faces=(0, 0, 1, 1, 0, 0), force=(g, 0, 0), lattice=L9)
+    out = oracle.run(G, W.rest_state(G.shape), 6000)
+    nu = (tau - 0.5) / 3.0
+    y = np.arange(1, ny - 1)
+    ua = g / (2 * nu) * ((y - 0.5) * (ny - 1.5 - y) - 0.25) + g / 2
+    assert np.abs(out[1, 0, 1:-1, 0] - ua).max() < 1e-9 * ua.max()
