@@ -1,7 +1,8 @@
 """Closed forms checked on the GPU path itself (not only through the
 oracle): the laminar Poiseuille profile between half-way walls and the
 decay of a linear shear wave, both exact for this scheme's linear
-dynamics (the same closed forms pin the oracle)."""
+dynamics, and the Taylor-Green decay rate 2 nu k^2 (the same closed forms
+pin the oracle)."""
 import numpy as np
 import pytest
 
@@ -82,3 +83,35 @@ def test_shear_wave_decay(kernel, lattice, order):
     amp = (st[1] * mode).sum() / (mode * mode).sum()
     amp0 = (st0[1] * mode).sum() / (mode * mode).sum()
     assert amp / amp0 == pytest.approx(lam ** steps, rel=2e-5)
+
+
+@pytest.mark.parametrize("kernel,lattice", VARIANTS)
+def test_taylor_green_decay_rate(kernel, lattice):
+    """The z-invariant Taylor-Green vortex (32^3, tau = 0.8, u0 = 0.01) decays
+    as exp(-2 nu k^2 t): the rate fitted over t in [20, 100] on the GPU path
+    is within 1e-3 of 2 nu k^2 (the initial Pi = 0 transient is over by
+    t = 20)."""
+    import torch
+    n, tau, u0 = 32, 0.8, 0.01
+    nz = 1 if lattice == 9 else n
+    case = W.Case("tgv", n, n, nz, tau, lattice=lattice)
+    st0 = W.rest_state(case.shape)
+    st0[1:3] = W.tgv_state(n, u0)[1:3, :nz]
+    st0 = W.to_fp32(st0)
+    mode = st0[1]
+    s = gpu_solver(case, kernel=kernel)
+    s.set_state(to_device_state(st0))
+    s.step(20)
+    ts, amps = [], []
+    for t in range(20, 101, 20):
+        if t > 20:
+            s.step(20)
+        st = from_device_state(s.get_state())
+        ts.append(t)
+        amps.append((st[1] * mode).sum() / (mode * mode).sum())
+    s.close()
+    torch.cuda.synchronize()
+    rate = -np.polyfit(ts, np.log(amps), 1)[0]
+    nu = CS2 * (float(np.float32(tau)) - 0.5)
+    k = 2 * np.pi / n
+    assert rate / (2 * nu * k * k) == pytest.approx(1.0, abs=1e-3)
