@@ -384,6 +384,8 @@ def main():
     ap.add_argument("--workload", default="channel", choices=sorted(WORKLOADS),
                     help="timed workload (default: the 384x192x192 channel)")
     ap.add_argument("--quick", action="store_true", help="only the timed workload (for profiling)")
+    ap.add_argument("--order", type=int, default=3, choices=(2, 3),
+                    help="Hermite order of the timed workload (2: the regularised collision, for profiling)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB 20 times (HBM counter calibration)")
@@ -414,7 +416,7 @@ def main():
     torch.cuda.set_device(0)
 
     case, st64 = WORKLOADS[args.workload](W)
-    s = _solver(case, 0, args.kernel)
+    s = _solver(case, 0, args.kernel, args.order)
     s.set_state(_device_state(st64))
     ms, wall = time_steps(s, args.steps, args.warmup)
     # the dominant kernel alone: HIP events around each of its launches, on
@@ -444,7 +446,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": case.name, "nodes": case.nodes, "lattice": {9: "D2Q9", 19: "D3Q19"}.get(case.lattice, "D3Q27"),
                    "tau": case.tau,
-                   "storage": "fp32", "faces": list(case.faces), "kernel": kname, "stable": rc == 0},
+                   "storage": "fp32", "faces": list(case.faces), "kernel": kname, "order": args.order,
+                   "stable": rc == 0},
         "fluid_mlups": round(fluid_nodes(case) * args.steps / (ms * 1e-3) / 1e6, 1),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
