@@ -268,6 +268,28 @@ __device__ __forceinline__ void load_node(const FieldPtrs<typename S::T>& f, uns
     for (int q = 4; q < 10; ++q) m[q] = S::load(ld_at(f.in[q], off), p.inv_scale[2]);
 }
 
+// The stored values of node n, left unconverted: a caller that loads the
+// next plane ahead keeps them in flight until the plane's build converts
+// them (a conversion right after the loads would wait for them there).
+template <class S>
+__device__ __forceinline__ void load_raw(const FieldPtrs<typename S::T>& f, unsigned n, typename S::T r[10]) {
+    unsigned off = n * (unsigned)sizeof(typename S::T);
+    // keep the offset opaque so that each load is one scalar base plus this
+    // shared offset (no per-field 64-bit addresses carried across planes)
+    asm volatile("" : "+v"(off));
+#pragma unroll
+    for (int q = 0; q < 10; ++q) r[q] = ld_at(f.in[q], off);
+}
+
+template <class S>
+__device__ __forceinline__ void convert_raw(const typename S::T r[10], const StepParams& p, float m[10]) {
+    m[0] = S::load(r[0], p.inv_scale[0]);
+#pragma unroll
+    for (int q = 1; q < 4; ++q) m[q] = S::load(r[q], p.inv_scale[1]);
+#pragma unroll
+    for (int q = 4; q < 10; ++q) m[q] = S::load(r[q], p.inv_scale[2]);
+}
+
 // Plane index of zp in [-1, nz]: one wrap for a periodic axis, else clamp.
 __device__ __forceinline__ int plane_index(int zp, int nz, bool periodic) {
     if (periodic) return zp < 0 ? zp + nz : (zp >= nz ? zp - nz : zp);

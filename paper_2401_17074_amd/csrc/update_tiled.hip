@@ -93,9 +93,26 @@ __global__ void __launch_bounds__(NTHREADS, TSLB_WAVES_PER_EU) update_tiled_kern
         return c;
     };
 
+    // What the next plane's build needs, loaded one plane ahead and left in
+    // flight until that build starts: the stored moments (unconverted), the
+    // acceleration of a force field and the plane's 1 - omega.  Converting
+    // 16-bit values right after their loads, or loading 1 - omega when the
+    // plane starts, would make the wave wait for its loads at that point.
+    typename S::T rcur[10];
+    float gcur[3] = {0.0f, 0.0f, 0.0f};
+    float ocur = p.one_minus_omega;
+    auto fetch = [&](unsigned col, int zq) {
+        const unsigned n = col + plane_nodes * (unsigned)zq;
+        load_raw<S>(f, n, rcur);
+        if constexpr (FIELD) {
+#pragma unroll
+            for (int a = 0; a < 3; ++a) gcur[a] = ld_at(f.g[a], n * 4u);
+        }
+        if (p.omo_z) ocur = p.omo_z[zq];
+    };
+
     Column c = column(t);
-    float mcur[10];  // moments of the plane being built
-    if (active) load_node<S>(f, c.col + plane_nodes * (unsigned)plane_index(c.zs - 1, nz, pz), p, mcur);
+    if (active) fetch(c.col, plane_index(c.zs - 1, nz, pz));
 
     for (;;) {
         // the block's next tile: its first plane is loaded while the last
@@ -124,31 +141,30 @@ __global__ void __launch_bounds__(NTHREADS, TSLB_WAVES_PER_EU) update_tiled_kern
             col_solid |= (c.wy == 0 && (g.lo_solid & 2)) || (c.wy == ny - 1 && (g.hi_solid & 2));
         }
         const float gon = col_solid ? 0.0f : 1.0f;
-        float gacc[3] = {gon * p.force[0], gon * p.force[1], gon * p.force[2]};
+        const float gacc[3] = {gon * p.force[0], gon * p.force[1], gon * p.force[2]};
 
-        // One plane zp with moments mcur: build and publish its populations,
-        // load the next plane (or the next tile's first plane) into mcur, add
+        // One plane zp: build and publish its populations from the fetched
+        // values, fetch the next plane (or the next tile's first plane), add
         // what arrives from plane zp to the output planes zp - 1 (aprev), zp
         // (acur) and zp + 1 (anext, which starts here), then store the
         // completed plane zp - 1.
         auto plane = [&](int zp, MomentSums& aprev, MomentSums& acur, MomentSums& anext) {
-            const unsigned node = c.col + plane_nodes * (unsigned)plane_index(zp, nz, pz);
             float G[27];
             if (active) {
-                if (FIELD) {
+                float m[10], gl[3];
+                convert_raw<S>(rcur, p, m);
 #pragma unroll
-                    for (int a = 0; a < 3; ++a) gacc[a] = gon * ld_at(f.g[a], node * 4u);
-                }
+                for (int a = 0; a < 3; ++a) gl[a] = FIELD ? gon * gcur[a] : gacc[a];
+                const float omo = ocur;
                 float A[NK];
-                const float omo = omo_at(p, plane_index(zp, nz, pz));
                 if (WALLS) {
                     // a wall plane (z walls) emits nothing either
                     const bool plane_solid = (zlo_wall && zp == 0) || (zhi_wall && zp == nz - 1);
                     const float gp = plane_solid ? 0.0f : 1.0f;
-                    const float gz[3] = {gp * gacc[0], gp * gacc[1], gp * gacc[2]};
-                    coefficients<ORDER, LAT>(mcur, gz, omo, A);
+                    const float gz[3] = {gp * gl[0], gp * gl[1], gp * gl[2]};
+                    coefficients<ORDER, LAT>(m, gz, omo, A);
                 } else {
-                    coefficients<ORDER, LAT>(mcur, gacc, omo, A);
+                    coefficients<ORDER, LAT>(m, gl, omo, A);
                 }
                 populations<LAT>(A, G);
                 if (WALLS && TSLB_FUSED_WALLS && interior && col_fluid) {
@@ -165,13 +181,13 @@ __global__ void __launch_bounds__(NTHREADS, TSLB_WAVES_PER_EU) update_tiled_kern
                 Unroll<0, 27>::run([&]<int I>() {
                     if constexpr (cx_of(I) != 0 || cy_of(I) != 0) lds[slot_of(I)][ly][lx] = G[I];
                 });
-                // mcur is dead once the coefficients are formed: the next
-                // plane's moments go straight into it and are in flight across
-                // the exchange and the gather
+                // the fetched values are dead once the coefficients are
+                // formed: the next plane's go into the same registers and are
+                // in flight across the exchange, the gather and the stores
                 if (zp + 1 <= ze)
-                    load_node<S>(f, c.col + plane_nodes * (unsigned)plane_index(zp + 1, nz, pz), p, mcur);
+                    fetch(c.col, plane_index(zp + 1, nz, pz));
                 else if (tn >= 0)
-                    load_node<S>(f, cn.col + plane_nodes * (unsigned)plane_index(cn.zs - 1, nz, pz), p, mcur);
+                    fetch(cn.col, plane_index(cn.zs - 1, nz, pz));
             }
             __syncthreads();
             // the 24 values arriving through LDS go to registers at once, so
