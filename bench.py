@@ -228,10 +228,18 @@ def cpu_baseline(case, st64, seconds_budget=12.0):
                       % (reps, idx.size, nplanes, case.name, dt)}
 
 
+STORAGE_NAMES = ("fp32", "fp16", "bf16")
+
+
+def _pmc_path(kernel_name, case_name, storage):
+    suffix = "" if storage == 0 else "_" + STORAGE_NAMES[storage]
+    return os.path.join(ROOT, "profiles", "pmc_%s_%s%s.json" % (kernel_name, case_name, suffix))
+
+
 def load_traffic(kernel_name, case_name, storage):
     """HBM bytes per launch from a committed rocprofv3 counter summary, only
     if it was taken on the current kernel sources."""
-    path = os.path.join(ROOT, "profiles", "pmc_%s_%s.json" % (kernel_name, case_name))
+    path = _pmc_path(kernel_name, case_name, storage)
     if not os.path.exists(path):
         return None
     try:
@@ -272,14 +280,14 @@ def summarize_pmc(args):
     ffac, wfac = copy_kib / cfetch, copy_kib / cwrite
     import workloads as W
     case, _ = WORKLOADS[args.workload](W)
-    algo = algorithmic_bytes(case, 0)
-    rec = {"kernel": kname, "workload": case.name, "storage": 0, "source_hash": _source_hash(),
+    algo = algorithmic_bytes(case, args.storage)
+    rec = {"kernel": kname, "workload": case.name, "storage": args.storage, "source_hash": _source_hash(),
            "fetch_kib_per_dispatch": fetch, "write_kib_per_dispatch": write, "dispatches": [nf, nw],
            "copy_fetch_factor": ffac, "copy_write_factor": wfac,
            "hbm_bytes_per_launch": (fetch * ffac + write * wfac) * 1024.0,
            "algorithmic_bytes_per_launch": algo}
     rec["traffic_over_algorithmic"] = rec["hbm_bytes_per_launch"] / algo
-    path = os.path.join(ROOT, "profiles", "pmc_%s_%s.json" % (kname, case.name))
+    path = _pmc_path(kname, case.name, args.storage)
     os.makedirs(os.path.dirname(path), exist_ok=True)
     json.dump(rec, open(path, "w"), indent=1)
     print(json.dumps(rec))
@@ -387,6 +395,8 @@ def main():
     ap.add_argument("--order", type=int, default=3, choices=(2, 3),
                     help="Hermite order of the timed workload (2: the regularised collision, for profiling)")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--storage", type=int, default=0, choices=(0, 1, 2),
+                    help="moment storage of the timed workload: 0 FP32 (default), 1 FP16, 2 BF16")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB 20 times (HBM counter calibration)")
     ap.add_argument("--summarize-pmc", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "COPY_FETCH_DIR", "COPY_WRITE_DIR"),
@@ -416,7 +426,7 @@ def main():
     torch.cuda.set_device(0)
 
     case, st64 = WORKLOADS[args.workload](W)
-    s = _solver(case, 0, args.kernel, args.order)
+    s = _solver(case, args.storage, args.kernel, args.order)
     s.set_state(_device_state(st64))
     ms, wall = time_steps(s, args.steps, args.warmup)
     # the dominant kernel alone: HIP events around each of its launches, on
@@ -429,7 +439,7 @@ def main():
     copy_gbs = copy_rate_gbs()
     kname = "update_d2q9" if case.lattice == 9 else ("update_tiled", "update_direct", "push")[args.kernel]
     per_launch_s = kms * 1e-3 / n_timed
-    algo = algorithmic_bytes(case, 0)
+    algo = algorithmic_bytes(case, args.storage)
     achieved = algo / per_launch_s / 1e9
     rec = {
         "metric": "MLUPS and % of HBM roofline (FP32 vs FP16-moment); adjoint step time / forward",
@@ -446,12 +456,12 @@ def main():
         "data": "synthetic",
         "config": {"workload": case.name, "nodes": case.nodes, "lattice": {9: "D2Q9", 19: "D3Q19"}.get(case.lattice, "D3Q27"),
                    "tau": case.tau,
-                   "storage": "fp32", "faces": list(case.faces), "kernel": kname, "order": args.order,
+                   "storage": STORAGE_NAMES[args.storage], "faces": list(case.faces), "kernel": kname, "order": args.order,
                    "stable": rc == 0},
         "fluid_mlups": round(fluid_nodes(case) * args.steps / (ms * 1e-3) / 1e6, 1),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": load_traffic(kname, case.name, 0),
+                     "traffic": load_traffic(kname, case.name, args.storage),
                      "algorithmic_bytes_per_launch": algo, "avg_launch_ms": round(per_launch_s * 1e3, 5),
                      "kernel": kname, "aux_ms_per_step": round(aux_ms / n_timed, 5),
                      "copy_gbs": round(copy_gbs, 1), "frac_of_copy": round(achieved / copy_gbs, 4)},
