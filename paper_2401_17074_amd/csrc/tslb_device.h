@@ -86,16 +86,22 @@ __device__ __forceinline__ long long wall_layer_index(const Geometry& g, int f, 
 // ------------------------------------------------------------------ storage
 // Stored field q of a node: FP32 as is; FP16 / BF16 hold value * scale[q]
 // rounded to nearest even.  Field 0 holds rho - 1.
+// convert / pack are the plain format conversions, load / store add the
+// field's scale (exact: the scales are powers of two).
 struct StoreF32 {
     using T = float;
+    __device__ __forceinline__ static float convert(T v) { return v; }
+    __device__ __forceinline__ static T pack(float v) { return v; }
     __device__ __forceinline__ static float load(T v, float) { return v; }
     __device__ __forceinline__ static T store(float v, float) { return v; }
 };
 
 struct StoreF16 {
     using T = __half;
-    __device__ __forceinline__ static float load(T v, float inv_scale) { return __half2float(v) * inv_scale; }
-    __device__ __forceinline__ static T store(float v, float scale) { return __float2half_rn(v * scale); }
+    __device__ __forceinline__ static float convert(T v) { return __half2float(v); }
+    __device__ __forceinline__ static T pack(float v) { return __float2half_rn(v); }
+    __device__ __forceinline__ static float load(T v, float inv_scale) { return convert(v) * inv_scale; }
+    __device__ __forceinline__ static T store(float v, float scale) { return pack(v * scale); }
 };
 
 // bfloat16 kept as raw 16-bit patterns: the upper half of a binary32 after
@@ -103,12 +109,10 @@ struct StoreF16 {
 // gfx950's own float-to-bfloat16 conversion (one instruction).
 struct StoreBF16 {
     using T = uint16_t;
-    __device__ __forceinline__ static float load(T v, float inv_scale) {
-        return __uint_as_float(((uint32_t)v) << 16) * inv_scale;
-    }
-    __device__ __forceinline__ static T store(float v, float scale) {
-        return __builtin_bit_cast(T, static_cast<__bf16>(v * scale));
-    }
+    __device__ __forceinline__ static float convert(T v) { return __uint_as_float(((uint32_t)v) << 16); }
+    __device__ __forceinline__ static T pack(float v) { return __builtin_bit_cast(T, static_cast<__bf16>(v)); }
+    __device__ __forceinline__ static float load(T v, float inv_scale) { return convert(v) * inv_scale; }
+    __device__ __forceinline__ static T store(float v, float scale) { return pack(v * scale); }
 };
 
 // ------------------------------------------------------------------ lattice
@@ -229,6 +233,30 @@ __device__ __forceinline__ void finalize(const MomentSums& a, float out[10]) {
     out[7] = (a.s[3] - a.j[0] * uy) * kInv;
     out[8] = (a.s[4] - a.j[0] * uz) * kInv;
     out[9] = (a.s[5] - a.j[1] * uz) * kInv;
+}
+
+// finalize() with the stored fields' scales s0 (drho), s1 (u), s2 (Pi)
+// applied: folded into the 1/SCALE factor where there is one (the same
+// values, since the scales are powers of two).
+template <int SCALE = 216>
+__device__ __forceinline__ void finalize_scaled(const MomentSums& a, float s0, float s1, float s2, float out[10]) {
+    constexpr float kInv = 1.0f / (float)SCALE;
+    const float k0 = kInv * s0, k2 = kInv * s2;
+    const float den = (float)SCALE + a.d;
+    float inv = __builtin_amdgcn_rcpf(den);
+    inv = inv * fmaf(-den, inv, 2.0f);
+    const float ux = a.j[0] * inv, uy = a.j[1] * inv, uz = a.j[2] * inv;
+    const float d3 = a.d * (1.0f / 3.0f);
+    out[0] = a.d * k0;
+    out[1] = ux * s1;
+    out[2] = uy * s1;
+    out[3] = uz * s1;
+    out[4] = (a.s[0] - a.j[0] * ux - d3) * k2;
+    out[5] = (a.s[1] - a.j[1] * uy - d3) * k2;
+    out[6] = (a.s[2] - a.j[2] * uz - d3) * k2;
+    out[7] = (a.s[3] - a.j[0] * uy) * k2;
+    out[8] = (a.s[4] - a.j[0] * uz) * k2;
+    out[9] = (a.s[5] - a.j[1] * uz) * k2;
 }
 
 // Compile-time loop over the 27 velocities.

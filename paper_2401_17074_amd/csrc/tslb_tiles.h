@@ -281,13 +281,16 @@ __device__ __forceinline__ void load_raw(const FieldPtrs<typename S::T>& f, unsi
     for (int q = 0; q < 10; ++q) r[q] = ld_at(f.in[q], off);
 }
 
+// Converted values of load_raw.  drho and u get their scales; Pi^neq is
+// left unscaled: the caller folds 1 / scale[2] into 1 - omega, the only
+// factor Pi^neq meets in coefficients() (exact, a power of two).
 template <class S>
 __device__ __forceinline__ void convert_raw(const typename S::T r[10], const StepParams& p, float m[10]) {
     m[0] = S::load(r[0], p.inv_scale[0]);
 #pragma unroll
     for (int q = 1; q < 4; ++q) m[q] = S::load(r[q], p.inv_scale[1]);
 #pragma unroll
-    for (int q = 4; q < 10; ++q) m[q] = S::load(r[q], p.inv_scale[2]);
+    for (int q = 4; q < 10; ++q) m[q] = S::convert(r[q]);
 }
 
 // Plane index of zp in [-1, nz]: one wrap for a periodic axis, else clamp.

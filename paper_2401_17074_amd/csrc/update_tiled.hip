@@ -155,7 +155,8 @@ __global__ void __launch_bounds__(NTHREADS, TSLB_WAVES_PER_EU) update_tiled_kern
                 convert_raw<S>(rcur, p, m);
 #pragma unroll
                 for (int a = 0; a < 3; ++a) gl[a] = FIELD ? gon * gcur[a] : gacc[a];
-                const float omo = ocur;
+                // 1 - omega with the stored Pi^neq scale folded in (see convert_raw)
+                const float omo = sizeof(typename S::T) == 4 ? ocur : ocur * p.inv_scale[2];
                 float A[NK];
                 if (WALLS) {
                     // a wall plane (z walls) emits nothing either
@@ -228,13 +229,13 @@ __global__ void __launch_bounds__(NTHREADS, TSLB_WAVES_PER_EU) update_tiled_kern
                     for (int k = 0; k < 6; ++k) side[4 + k] = aprev.s[k];
                 } else if (fl) {
                     float out[10];
-                    finalize<LAT == 19 ? 36 : 216>(aprev, out);
+                    if constexpr (sizeof(typename S::T) == 4)
+                        finalize<LAT == 19 ? 36 : 216>(aprev, out);
+                    else
+                        finalize_scaled<LAT == 19 ? 36 : 216>(aprev, p.scale[0], p.scale[1], p.scale[2], out);
                     const unsigned on = (c.col + plane_nodes * (unsigned)zo) * (unsigned)sizeof(typename S::T);
-                    store_out(at(f.out[0], on), S::store(out[0], p.scale[0]));
 #pragma unroll
-                    for (int q = 1; q < 4; ++q) store_out(at(f.out[q], on), S::store(out[q], p.scale[1]));
-#pragma unroll
-                    for (int q = 4; q < 10; ++q) store_out(at(f.out[q], on), S::store(out[q], p.scale[2]));
+                    for (int q = 0; q < 10; ++q) store_out(at(f.out[q], on), S::pack(out[q]));
                 }
             }
         };
