@@ -192,9 +192,9 @@ __global__ void __launch_bounds__(NTHREADS, TSLB_WAVES_PER_EU) update_tiled_kern
             }
             __syncthreads();
             // the 24 values arriving through LDS go to registers at once, so
-            // the buffer is free again after the second barrier and the gather
-            // sums, the stores and the next plane's build form one
-            // barrier-free phase
+            // the buffer is free again after the second barrier and the
+            // stores and the next plane's build (with FP32 storage, also the
+            // gather sums) form one barrier-free phase
             float F[3][3][3];  // [cz + 1][cy + 1][cx + 1]
             if (interior) {
                 Unroll<0, 27>::run([&]<int I>() {
@@ -205,11 +205,24 @@ __global__ void __launch_bounds__(NTHREADS, TSLB_WAVES_PER_EU) update_tiled_kern
                         F[Z + 1][Y + 1][X + 1] = lds[slot_of(I)][ly - Y][lx - X];
                 });
             }
+            // With 16-bit storage the kernel is compute-bound: the sums are
+            // formed before the barrier, so one wave's adds overlap the other
+            // waves' LDS reads.  With FP32 storage they come after it.
+            constexpr bool kSumFirst = sizeof(typename S::T) == 2;
+            if constexpr (kSumFirst) {
+                if (interior) {
+                    add_slice<-1>(F[0], aprev);
+                    add_slice<0>(F[1], acur);
+                    add_slice<1, true>(F[2], anext);
+                }
+            }
             __syncthreads();
-            if (interior) {
-                add_slice<-1>(F[0], aprev);
-                add_slice<0>(F[1], acur);
-                add_slice<1, true>(F[2], anext);
+            if constexpr (!kSumFirst) {
+                if (interior) {
+                    add_slice<-1>(F[0], aprev);
+                    add_slice<0>(F[1], acur);
+                    add_slice<1, true>(F[2], anext);
+                }
             }
             const int zo = zp - 1;
             if (interior && zo >= zs && zo < ze) {
