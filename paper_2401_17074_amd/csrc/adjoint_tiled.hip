@@ -230,12 +230,17 @@ __global__ void __launch_bounds__(NTHREADS, TSLB_WAVES_PER_EU)
             const bool fl = col_fluid_any && !(zlo_wall && zo == 0) && !(zhi_wall && zo == nz - 1) &&
                             is_fluid(g, gx, gy, zo);
             float out[10], lg[3] = {0.0f, 0.0f, 0.0f};
+            float dg_old[3] = {0.0f, 0.0f, 0.0f};  // read with the moments, not after the stores
             if (fl) {
                 float m[10], gg[3];
 #pragma unroll
                 for (int k = 0; k < 10; ++k) m[k] = st0[k * N + on];
 #pragma unroll
                 for (int a = 0; a < 3; ++a) gg[a] = FIELD ? p.gfield[a * N + on] : p.force[a];
+                if (DG) {
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) dg_old[a] = dg[a * N + on];
+                }
                 float L[NK];
 #pragma unroll
                 for (int k = 0; k < NK; ++k) L[k] = aprev.L[k] * kInv216;
@@ -248,7 +253,7 @@ __global__ void __launch_bounds__(NTHREADS, TSLB_WAVES_PER_EU)
             for (int k = 0; k < 10; ++k) lam0[k * N + on] = out[k];
             if (DG && fl) {
 #pragma unroll
-                for (int a = 0; a < 3; ++a) dg[a * N + on] += lg[a];
+                for (int a = 0; a < 3; ++a) dg[a * N + on] = dg_old[a] + lg[a];
             }
         }
         aprev.zero();
