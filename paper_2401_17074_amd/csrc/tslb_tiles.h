@@ -222,9 +222,13 @@ __device__ __forceinline__ void add_slice(const float F[3][3], MomentSums& a) {
 
 // Output stores: the new level is not read again by this launch, so it may
 // bypass L2 allocation (non-temporal) and leave the cache to the halo reads.
-template <class T>
+// That pays when a grid row is a whole number of 128-B cache lines; with
+// other row lengths a wave's row straddles lines that the neighbouring tile
+// completes, and plain stores let L2 merge the two halves before they go to
+// memory (the launch decides, NT).
+template <bool NT, class T>
 __device__ __forceinline__ void store_out(T* p, T v) {
-    if constexpr (TSLB_NT_STORE) {
+    if constexpr (NT && TSLB_NT_STORE) {
         if constexpr (sizeof(T) == 4)
             __builtin_nontemporal_store(__builtin_bit_cast(float, v), reinterpret_cast<float*>(p));
         else

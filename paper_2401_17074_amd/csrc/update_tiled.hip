@@ -31,7 +31,7 @@ namespace {
 using namespace tile;
 
 
-template <class S, bool WALLS, bool FIELD, int ORDER, int LAT>
+template <class S, bool WALLS, bool FIELD, int ORDER, int LAT, bool NT>
 __global__ void __launch_bounds__(NTHREADS, TSLB_WAVES_PER_EU) update_tiled_kernel(const FieldPtrs<typename S::T> f, StepParams p,
                                                                    int tiles_x, int tiles_y, int tiles_z, int TZ) {
     __shared__ float lds[NSLOT][LY][LX];
@@ -248,7 +248,7 @@ __global__ void __launch_bounds__(NTHREADS, TSLB_WAVES_PER_EU) update_tiled_kern
                         finalize_scaled<LAT == 19 ? 36 : 216>(aprev, p.scale[0], p.scale[1], p.scale[2], out);
                     const unsigned on = (c.col + plane_nodes * (unsigned)zo) * (unsigned)sizeof(typename S::T);
 #pragma unroll
-                    for (int q = 0; q < 10; ++q) store_out(at(f.out[q], on), S::pack(out[q]));
+                    for (int q = 0; q < 10; ++q) store_out<NT>(at(f.out[q], on), S::pack(out[q]));
                 }
             }
         };
@@ -341,8 +341,15 @@ hipError_t launch_t(const void* in, void* out, const StepParams& p, hipStream_t 
     const unsigned nblk = (unsigned)tiles_x * tiles_y * tiles_z;
     if (p.geo.N >= (1LL << 30)) return hipErrorInvalidValue;  // 32-bit node offsets
     const FieldPtrs<typename S::T> f = field_ptrs<S>(in, out, p);
-    hipLaunchKernelGGL((update_tiled_kernel<S, WALLS, FIELD, ORDER, LAT>), dim3(walk_grid(nblk)), dim3(NTHREADS), 0, s, f,
-                       p, tiles_x, tiles_y, tiles_z, TZ);
+    // non-temporal output stores only when every row starts on a cache line
+    const bool nt = ((long long)p.geo.n[0] * (long long)sizeof(typename S::T)) % 128 == 0;
+    const dim3 grid(walk_grid(nblk)), block(NTHREADS);
+    if (nt)
+        hipLaunchKernelGGL((update_tiled_kernel<S, WALLS, FIELD, ORDER, LAT, true>), grid, block, 0, s, f, p, tiles_x,
+                           tiles_y, tiles_z, TZ);
+    else
+        hipLaunchKernelGGL((update_tiled_kernel<S, WALLS, FIELD, ORDER, LAT, false>), grid, block, 0, s, f, p, tiles_x,
+                           tiles_y, tiles_z, TZ);
     return hipGetLastError();
 }
 
