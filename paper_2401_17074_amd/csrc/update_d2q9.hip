@@ -138,7 +138,20 @@ __device__ __forceinline__ int wrap_clamp(int v, int n, bool periodic) {
     return v < 0 ? 0 : (v >= n ? n - 1 : v);
 }
 
-template <class S, int ORDER, bool FIELD>
+// Output stores, non-temporal (the new level is not read again by this
+// launch) when every grid row is a whole number of 128-B cache lines, plain
+// otherwise (a strip's row then straddles lines its neighbour completes).
+template <bool NT, class T>
+__device__ __forceinline__ void out_store(T* p, T v) {
+    if constexpr (!NT)
+        *p = v;
+    else if constexpr (sizeof(T) == 4)
+        __builtin_nontemporal_store(__builtin_bit_cast(float, v), reinterpret_cast<float*>(p));
+    else
+        __builtin_nontemporal_store(__builtin_bit_cast(unsigned short, v), reinterpret_cast<unsigned short*>(p));
+}
+
+template <class S, int ORDER, bool FIELD, bool NT>
 __global__ void __launch_bounds__(kD2Block) update_d2q9_kernel(const Fields2<typename S::T> f, StepParams p, int strips,
                                                                int segments, int seg_rows) {
     using T = typename S::T;
@@ -262,12 +275,12 @@ __global__ void __launch_bounds__(kD2Block) update_d2q9_kernel(const Fields2<typ
         const float ux = a.jx * inv, uy = a.jy * inv, d3 = a.d * (1.0f / 3.0f);
         constexpr float k36 = 1.0f / 36.0f;
         const unsigned oo = (unsigned)(x + nx * yo) * (unsigned)sizeof(T);
-        *(T*)((char*)f.out[0] + oo) = S::store(a.d * k36, p.scale[0]);
-        *(T*)((char*)f.out[1] + oo) = S::store(ux, p.scale[1]);
-        *(T*)((char*)f.out[2] + oo) = S::store(uy, p.scale[1]);
-        *(T*)((char*)f.out[3] + oo) = S::store((a.sxx - a.jx * ux - d3) * k36, p.scale[2]);
-        *(T*)((char*)f.out[4] + oo) = S::store((a.syy - a.jy * uy - d3) * k36, p.scale[2]);
-        *(T*)((char*)f.out[5] + oo) = S::store((a.sxy - a.jx * uy) * k36, p.scale[2]);
+        out_store<NT>((T*)((char*)f.out[0] + oo), S::store(a.d * k36, p.scale[0]));
+        out_store<NT>((T*)((char*)f.out[1] + oo), S::store(ux, p.scale[1]));
+        out_store<NT>((T*)((char*)f.out[2] + oo), S::store(uy, p.scale[1]));
+        out_store<NT>((T*)((char*)f.out[3] + oo), S::store((a.sxx - a.jx * ux - d3) * k36, p.scale[2]));
+        out_store<NT>((T*)((char*)f.out[4] + oo), S::store((a.syy - a.jy * uy - d3) * k36, p.scale[2]));
+        out_store<NT>((T*)((char*)f.out[5] + oo), S::store((a.sxy - a.jx * uy) * k36, p.scale[2]));
     };
 
     Sums2 a0, a1, a2;
@@ -297,11 +310,18 @@ hipError_t launch_o(const void* in, void* out, const StepParams& p, int strips, 
         f.out[k] = (T*)out + field[k] * N;
     }
     for (int a = 0; a < 2; ++a) f.g[a] = p.gfield ? p.gfield + a * N : nullptr;
-    if (p.gfield)
-        hipLaunchKernelGGL((update_d2q9_kernel<S, ORDER, true>), dim3(grid), dim3(kD2Block), 0, s, f, p, strips, segments,
-                           seg_rows);
+    const bool nt = ((long long)p.geo.n[0] * (long long)sizeof(T)) % 128 == 0;
+    if (p.gfield && nt)
+        hipLaunchKernelGGL((update_d2q9_kernel<S, ORDER, true, true>), dim3(grid), dim3(kD2Block), 0, s, f, p, strips,
+                           segments, seg_rows);
+    else if (p.gfield)
+        hipLaunchKernelGGL((update_d2q9_kernel<S, ORDER, true, false>), dim3(grid), dim3(kD2Block), 0, s, f, p, strips,
+                           segments, seg_rows);
+    else if (nt)
+        hipLaunchKernelGGL((update_d2q9_kernel<S, ORDER, false, true>), dim3(grid), dim3(kD2Block), 0, s, f, p, strips,
+                           segments, seg_rows);
     else
-        hipLaunchKernelGGL((update_d2q9_kernel<S, ORDER, false>), dim3(grid), dim3(kD2Block), 0, s, f, p, strips,
+        hipLaunchKernelGGL((update_d2q9_kernel<S, ORDER, false, false>), dim3(grid), dim3(kD2Block), 0, s, f, p, strips,
                            segments, seg_rows);
     return hipGetLastError();
 }
