@@ -43,8 +43,13 @@ __global__ void ghost_fill_kernel(typename S::T* __restrict__ st, StepParams p, 
     }
     const long long n = c[0] + (long long)g.n[0] * (c[1] + (long long)g.n[1] * c[2]);
     const long long nf = cf[0] + (long long)g.n[0] * (cf[1] + (long long)g.n[1] * cf[2]);
+    // all ten loads first: the source is an interior node this kernel never
+    // writes, and one wait replaces ten load-store round trips
+    typename S::T v[10];
 #pragma unroll
-    for (int k = 0; k < 10; ++k) st[k * g.N + n] = st[k * g.N + nf];
+    for (int k = 0; k < 10; ++k) v[k] = st[k * g.N + nf];
+#pragma unroll
+    for (int k = 0; k < 10; ++k) st[k * g.N + n] = v[k];
     float u[3];
     if (inlet_velocity(g, q, p.dims, t, n, c, u))
         for (int a = 0; a < p.dims; ++a) st[(1 + a) * g.N + n] = S::store(u[a], p.scale[1]);
