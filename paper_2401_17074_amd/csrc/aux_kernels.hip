@@ -12,10 +12,15 @@ namespace {
 // ghost node takes the ten stored values of its interior neighbour
 // (coordinates clamped into the interior along every ghost axis); nodes of
 // an inlet disc then get the imposed velocity with the seeded perturbation.
+//
+// With x_done set the tiled update has already written the ghost nodes of
+// the x faces that lie on no other ghost face (each from the interior node
+// next to it, the value it had just computed): those only get the inlet
+// velocity where it applies.
 template <class S>
 __global__ void ghost_fill_kernel(typename S::T* __restrict__ st, StepParams p, InletParams q, int64_t t,
                                   long long off1, long long off2, long long off3, long long off4,
-                                  long long off5, long long total) {
+                                  long long off5, long long total, int x_done) {
     const Geometry& g = p.geo;
     const long long tid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (tid >= total) return;
@@ -43,6 +48,12 @@ __global__ void ghost_fill_kernel(typename S::T* __restrict__ st, StepParams p, 
     }
     const long long n = c[0] + (long long)g.n[0] * (c[1] + (long long)g.n[1] * c[2]);
     const long long nf = cf[0] + (long long)g.n[0] * (cf[1] + (long long)g.n[1] * cf[2]);
+    float u[3];
+    if (x_done && d == 0 && cf[1] == c[1] && cf[2] == c[2]) {
+        if (inlet_velocity(g, q, p.dims, t, n, c, u))
+            for (int a = 0; a < p.dims; ++a) st[(1 + a) * g.N + n] = S::store(u[a], p.scale[1]);
+        return;
+    }
     // all ten loads first: the source is an interior node this kernel never
     // writes, and one wait replaces ten load-store round trips
     typename S::T v[10];
@@ -50,7 +61,6 @@ __global__ void ghost_fill_kernel(typename S::T* __restrict__ st, StepParams p, 
     for (int k = 0; k < 10; ++k) v[k] = st[k * g.N + nf];
 #pragma unroll
     for (int k = 0; k < 10; ++k) st[k * g.N + n] = v[k];
-    float u[3];
     if (inlet_velocity(g, q, p.dims, t, n, c, u))
         for (int a = 0; a < p.dims; ++a) st[(1 + a) * g.N + n] = S::store(u[a], p.scale[1]);
 }
@@ -333,7 +343,7 @@ __global__ void __launch_bounds__(256) adjoint_step_kernel(const float* __restri
 }
 
 template <class S>
-hipError_t ghost_fill_t(void* st, const StepParams& p, const InletParams& q, int64_t t, hipStream_t s) {
+hipError_t ghost_fill_t(void* st, const StepParams& p, const InletParams& q, int64_t t, int x_done, hipStream_t s) {
     long long area[6];
     for (int f = 0; f < 6; ++f) {
         const int d = f >> 1, d1 = d == 0 ? 1 : 0, d2 = d == 2 ? 1 : 2;
@@ -345,18 +355,18 @@ hipError_t ghost_fill_t(void* st, const StepParams& p, const InletParams& q, int
     const int block = 256;
     const long long grid = (off[6] + block - 1) / block;
     hipLaunchKernelGGL(ghost_fill_kernel<S>, dim3((unsigned)grid), dim3(block), 0, s, (typename S::T*)st, p, q, t,
-                       off[1], off[2], off[3], off[4], off[5], off[6]);
+                       off[1], off[2], off[3], off[4], off[5], off[6], x_done);
     return hipGetLastError();
 }
 
 }  // namespace
 
 hipError_t launch_ghost_fill(int storage, void* st, const StepParams& p, const InletParams& q, int64_t t,
-                             hipStream_t s) {
+                             int x_done, hipStream_t s) {
     switch (storage) {
-    case 0: return ghost_fill_t<StoreF32>(st, p, q, t, s);
-    case 1: return ghost_fill_t<StoreF16>(st, p, q, t, s);
-    case 2: return ghost_fill_t<StoreBF16>(st, p, q, t, s);
+    case 0: return ghost_fill_t<StoreF32>(st, p, q, t, x_done, s);
+    case 1: return ghost_fill_t<StoreF16>(st, p, q, t, x_done, s);
+    case 2: return ghost_fill_t<StoreBF16>(st, p, q, t, x_done, s);
     }
     return hipErrorInvalidValue;
 }

@@ -74,9 +74,13 @@ int ensure_staging(tslb_ctx* h) {
     return TSLB_OK;
 }
 
-int fill_ghosts(tslb_ctx* h, void* st, hipStream_t s) {
+// after_update: st was just written by run_update / run_main_update, so the
+// tiled D3 update may already have refilled the plain x-face ghost nodes
+int fill_ghosts(tslb_ctx* h, void* st, hipStream_t s, bool after_update = false) {
     if (!h->has_ghosts) return TSLB_OK;
-    HIP_TRY(launch_ghost_fill(h->storage, st, h->p, h->inlet, h->t, s));
+    const int x_done = after_update && h->kernel == 0 && h->lattice != TSLB_D2Q9 &&
+                       tslb::tiled_writes_x_ghosts(h->storage, h->p);
+    HIP_TRY(launch_ghost_fill(h->storage, st, h->p, h->inlet, h->t, x_done, s));
     return TSLB_OK;
 }
 
@@ -458,7 +462,7 @@ int tslb_step(tslb_handle h, int nsteps, void* stream) {
         HIP_TRY(run_update(h, in, out, s));
         h->cur = 1 - h->cur;
         h->t += 1;
-        int rc = fill_ghosts(h, out, s);
+        int rc = fill_ghosts(h, out, s, true);
         if (rc) return rc;
     }
     return TSLB_OK;
@@ -491,7 +495,7 @@ int tslb_step_timed(tslb_handle h, int nsteps, double ms[2], void* stream) {
         }
         h->cur = 1 - h->cur;
         h->t += 1;
-        rc = fill_ghosts(h, out, s);
+        rc = fill_ghosts(h, out, s, true);
         if (rc == TSLB_OK && hipEventRecord(ev[3 * k + 2], s) != hipSuccess) rc = fail(TSLB_E_HIP, "hipEventRecord failed");
     }
     if (rc == TSLB_OK) {

@@ -29,8 +29,13 @@ hipError_t launch_stats_jet(const double* fs, const Geometry& g, int axis, float
                             float* uc, float* rhalf, hipStream_t s);
 // Completes the wall-adjacent nodes after launch_update_tiled (walls only).
 hipError_t launch_wall_fixup(int storage, const void* in, void* out, const StepParams& p, hipStream_t s);
+// x_done: the tiled update has written the ghost nodes of the x faces that
+// lie on no other ghost face (inlet velocities are still imposed here)
 hipError_t launch_ghost_fill(int storage, void* st, const StepParams& p, const InletParams& q, int64_t t,
-                             hipStream_t s);
+                             int x_done, hipStream_t s);
+// Does launch_update_tiled write those x-face ghost nodes for this grid and
+// storage (rows of whole cache lines, no walls, no force field)?
+bool tiled_writes_x_ghosts(int storage, const StepParams& p);
 hipError_t launch_pack(int storage, const float* rho, const float* u, const float* pi, int rho_dev, void* st,
                        const StepParams& p, hipStream_t s);
 hipError_t launch_unpack(int storage, const void* st, float* rho, float* u, float* pi, int rho_dev,

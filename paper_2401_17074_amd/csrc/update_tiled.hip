@@ -31,7 +31,9 @@ namespace {
 using namespace tile;
 
 
-template <class S, bool WALLS, bool FIELD, int ORDER, int LAT, bool NT>
+// MODE 0: plain output stores; 1: non-temporal ones; 2: non-temporal, and
+// the fluid nodes next to x ghost faces also write those ghost nodes.
+template <class S, bool WALLS, bool FIELD, int ORDER, int LAT, int MODE>
 __global__ void __launch_bounds__(NTHREADS, TSLB_WAVES_PER_EU) update_tiled_kernel(const FieldPtrs<typename S::T> f, StepParams p,
                                                                    int tiles_x, int tiles_y, int tiles_z, int TZ) {
     __shared__ float lds[NSLOT][LY][LX];
@@ -248,7 +250,25 @@ __global__ void __launch_bounds__(NTHREADS, TSLB_WAVES_PER_EU) update_tiled_kern
                         finalize_scaled<LAT == 19 ? 36 : 216>(aprev, p.scale[0], p.scale[1], p.scale[2], out);
                     const unsigned on = (c.col + plane_nodes * (unsigned)zo) * (unsigned)sizeof(typename S::T);
 #pragma unroll
-                    for (int q = 0; q < 10; ++q) store_out<NT>(at(f.out[q], on), S::pack(out[q]));
+                    for (int q = 0; q < 10; ++q) store_out<(MODE > 0)>(at(f.out[q], on), S::pack(out[q]));
+                    if constexpr (MODE == 2) {
+                        // A ghost node of an x face next to this fluid node
+                        // takes its values (Section 2.3 refill; an inlet's
+                        // velocity is imposed by the refill pass): stored here,
+                        // into the cache line this row's stores fill anyway.
+                        // This node is fluid, so that ghost lies on no other
+                        // ghost face.
+                        if ((g.lo_ghost & 1) && gx == 1) {
+                            const unsigned og = on - (unsigned)sizeof(typename S::T);
+#pragma unroll
+                            for (int q = 0; q < 10; ++q) store_out<true>(at(f.out[q], og), S::pack(out[q]));
+                        }
+                        if ((g.hi_ghost & 1) && gx == nx - 2) {
+                            const unsigned og = on + (unsigned)sizeof(typename S::T);
+#pragma unroll
+                            for (int q = 0; q < 10; ++q) store_out<true>(at(f.out[q], og), S::pack(out[q]));
+                        }
+                    }
                 }
             }
         };
@@ -332,6 +352,12 @@ __global__ void __launch_bounds__(256) wall_fixup_kernel(const FieldPtrs<typenam
     for (int q = 4; q < 10; ++q) *at(f.out[q], on) = S::store(out[q], p.scale[2]);
 }
 
+template <class S>
+bool rows_whole_lines(const StepParams& p) {
+    return ((long long)p.geo.n[0] * (long long)sizeof(typename S::T)) % 128 == 0;
+}
+inline bool x_ghost_faces(const StepParams& p) { return ((p.geo.lo_ghost | p.geo.hi_ghost) & 1) != 0; }
+
 template <class S, bool WALLS, bool FIELD, int ORDER, int LAT>
 hipError_t launch_t(const void* in, void* out, const StepParams& p, hipStream_t s) {
     const int tiles_x = (p.geo.n[0] + TX - 1) / TX;
@@ -342,13 +368,20 @@ hipError_t launch_t(const void* in, void* out, const StepParams& p, hipStream_t 
     if (p.geo.N >= (1LL << 30)) return hipErrorInvalidValue;  // 32-bit node offsets
     const FieldPtrs<typename S::T> f = field_ptrs<S>(in, out, p);
     // non-temporal output stores only when every row starts on a cache line
-    const bool nt = ((long long)p.geo.n[0] * (long long)sizeof(typename S::T)) % 128 == 0;
+    const bool nt = rows_whole_lines<S>(p);
     const dim3 grid(walk_grid(nblk)), block(NTHREADS);
+    if constexpr (!WALLS && !FIELD) {
+        if (nt && x_ghost_faces(p)) {
+            hipLaunchKernelGGL((update_tiled_kernel<S, false, false, ORDER, LAT, 2>), grid, block, 0, s, f, p, tiles_x,
+                               tiles_y, tiles_z, TZ);
+            return hipGetLastError();
+        }
+    }
     if (nt)
-        hipLaunchKernelGGL((update_tiled_kernel<S, WALLS, FIELD, ORDER, LAT, true>), grid, block, 0, s, f, p, tiles_x,
+        hipLaunchKernelGGL((update_tiled_kernel<S, WALLS, FIELD, ORDER, LAT, 1>), grid, block, 0, s, f, p, tiles_x,
                            tiles_y, tiles_z, TZ);
     else
-        hipLaunchKernelGGL((update_tiled_kernel<S, WALLS, FIELD, ORDER, LAT, false>), grid, block, 0, s, f, p, tiles_x,
+        hipLaunchKernelGGL((update_tiled_kernel<S, WALLS, FIELD, ORDER, LAT, 0>), grid, block, 0, s, f, p, tiles_x,
                            tiles_y, tiles_z, TZ);
     return hipGetLastError();
 }
@@ -396,6 +429,12 @@ hipError_t fixup_s(const void* in, void* out, const StepParams& p, hipStream_t s
 }
 
 bool tiled_uses_wall_side() { return TSLB_FUSED_WALLS == 0; }
+
+bool tiled_writes_x_ghosts(int storage, const StepParams& p) {
+    const bool walls = (p.geo.lo_solid | p.geo.hi_solid) != 0;
+    const bool nt = storage == 0 ? rows_whole_lines<StoreF32>(p) : rows_whole_lines<StoreF16>(p);
+    return !walls && p.gfield == nullptr && nt && x_ghost_faces(p);
+}
 
 hipError_t launch_wall_fixup(int storage, const void* in, void* out, const StepParams& p, hipStream_t s) {
     switch (storage) {
