@@ -129,7 +129,10 @@ int tslb_create(int nx, int ny, int nz, int lattice, float tau, const float forc
 int tslb_destroy(tslb_handle h);
 
 /* Overwrite the state at the current level with rho (N), u (3N) and Pi^neq
- * (6N, or NULL for zero).  flags: TSLB_DEVICE if the arrays are device
+ * (6N, or NULL for zero): the ten hydrodynamic moments that are the only
+ * stored variables of the scheme (Section 2.2, the storage remark; Pi^neq is
+ * the pre-collision non-equilibrium second moment the reconstruction of
+ * Eq. (noneqts) starts from).  flags: TSLB_DEVICE if the arrays are device
  * memory (else host; the call then synchronises the stream),
  * TSLB_RHO_DEVIATION if `rho` holds rho - 1.  Values are rounded to the
  * storage format; ghost layers are then refilled from the interior (so input
@@ -138,14 +141,20 @@ int tslb_destroy(tslb_handle h);
 int tslb_set_moments(tslb_handle h, const float *rho, const float *u, const float *pineq, int flags,
                      void *stream);
 
-/* Read the current state (all nodes; ghosts hold their fill values, solid
+/* Read the current state, the moments of Section 2.2 (rho, u, Pi^neq) at
+ * level t (all nodes; ghosts hold their fill values of Section 2.3, solid
  * nodes the rest state).  Any output pointer may be NULL.  Same flags as
  * tslb_set_moments; host reads synchronise the stream.                      */
 int tslb_get_moments(tslb_handle h, float *rho, float *u, float *pineq, int flags, void *stream);
 
 /* Use a per-node body-acceleration field g (3N floats, device memory,
  * copied into the handle) instead of the uniform force; NULL returns to the
- * uniform force given at creation.                                          */
+ * uniform force given at creation.  The forcing is the local term of
+ * Section 3.1, w_i rho c_i.g / cs2 added to every population a node emits,
+ * with rho and g of the emitting node (no half-force velocity shift), so a
+ * step changes the total momentum by exactly sum rho g over fluid nodes.
+ * The field also parameterises the adjoint (tslb_adjoint_step dg_accum).
+ * Errors: TSLB_E_NOMEM (first use allocates 3N floats).                    */
 int tslb_set_force_field(tslb_handle h, const float *g, void *stream);
 
 /* Relaxation time per z plane: tau_z holds nz values (host memory, each

@@ -127,27 +127,57 @@ __global__ void __launch_bounds__(kStatBlock) field_moments_kernel(const double*
 
 constexpr int kJetBlock = 256;
 
-// One block per cross-section j along `axis`.  Bins of k = floor(r) hold
-// the count, the summed radius and the summed mean axial velocity (LDS,
-// FP64 atomics); then thread 0 walks the bins.
+// One block per cross-section j along `axis`.  Bin k = floor(r) holds the
+// count, the summed radius and the summed mean axial velocity of its nodes.
+// Each bin is owned by one thread, which visits the nodes of its annulus
+// k <= r < k + 1 row by row and, within a row, in increasing coordinate
+// (a fixed order, so the sums do not depend on scheduling); thread 0 then
+// walks the bins.
 __global__ void __launch_bounds__(kJetBlock) jet_axis_kernel(const double* __restrict__ s, Geometry g, int axis,
                                                              float c1, float c2, double inv_ns, int nbins,
                                                              float* __restrict__ uc, float* __restrict__ rhalf) {
     extern __shared__ double bins[];  // 3 * nbins: count, sum r, sum u
     const int j = blockIdx.x;
-    for (int b = threadIdx.x; b < 3 * nbins; b += kJetBlock) bins[b] = 0.0;
-    __syncthreads();
     const int d1 = axis == 0 ? 1 : 0, d2 = axis == 2 ? 1 : 2;
-    const long long plane = (long long)g.n[d1] * g.n[d2];
-    for (long long k = threadIdx.x; k < plane; k += kJetBlock) {
-        int c[3];
-        const long long n = plane_node(g, axis, j, k, c);
-        const double r1 = (double)c[d1] - (double)c1, r2 = (double)c[d2] - (double)c2;
-        const double r = sqrt(r1 * r1 + r2 * r2);
-        const int b = (int)floor(r);
-        atomicAdd(&bins[b], 1.0);
-        atomicAdd(&bins[nbins + b], r);
-        atomicAdd(&bins[2 * nbins + b], s[(long long)axis * g.N + n] * inv_ns);
+    const int n1 = g.n[d1], n2 = g.n[d2];
+    const double* __restrict__ ua = s + (long long)axis * g.N;
+    for (int b = threadIdx.x; b < nbins; b += kJetBlock) {
+        double cnt = 0.0, sr = 0.0, su = 0.0;
+        const double bo = (double)b + 1.0, bi = (double)b;
+        const int y0 = max(0, (int)floor((double)c2 - bo) - 1), y1 = min(n2 - 1, (int)ceil((double)c2 + bo) + 1);
+        for (int y = y0; y <= y1; ++y) {
+            const double r2 = (double)y - (double)c2;
+            const double qo = bo * bo - r2 * r2;
+            if (qo <= 0.0) continue;  // every node of this row has r >= b + 1
+            const double qi = bi * bi - r2 * r2;
+            const double so = sqrt(qo), si = qi > 0.0 ? sqrt(qi) : 0.0;
+            // the annulus meets the row in [c1 - so, c1 - si] and [c1 + si, c1 + so];
+            // both ranges are widened by one node and every candidate is tested
+            const int xl0 = max(0, (int)floor((double)c1 - so) - 1);
+            const int xl1 = min(n1 - 1, (int)ceil((double)c1 - si) + 1);
+            int xr0 = max(0, (int)floor((double)c1 + si) - 1);
+            const int xr1 = min(n1 - 1, (int)ceil((double)c1 + so) + 1);
+            if (xr0 <= xl1) xr0 = xl1 + 1;
+            for (int pass = 0; pass < 2; ++pass) {
+                const int xa = pass == 0 ? xl0 : xr0, xb = pass == 0 ? xl1 : xr1;
+                for (int x = xa; x <= xb; ++x) {
+                    const double r1 = (double)x - (double)c1;
+                    const double r = sqrt(r1 * r1 + r2 * r2);
+                    if ((int)floor(r) != b) continue;
+                    int c[3];
+                    c[axis] = j;
+                    c[d1] = x;
+                    c[d2] = y;
+                    const long long n = c[0] + (long long)g.n[0] * (c[1] + (long long)g.n[1] * c[2]);
+                    cnt += 1.0;
+                    sr += r;
+                    su += ua[n] * inv_ns;
+                }
+            }
+        }
+        bins[b] = cnt;
+        bins[nbins + b] = sr;
+        bins[2 * nbins + b] = su;
     }
     __syncthreads();
     if (threadIdx.x != 0) return;
