@@ -188,6 +188,25 @@ int tslb_set_time(tslb_handle h, int64_t t);
  * still written) if any stored fluid moment is NaN or Inf.                   */
 int tslb_reduce(tslb_handle h, double out[5], void *stream);
 
+/* For callers that cannot allocate device memory or synchronise (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the sums of tslb_reduce, in the same fixed order and bit-identical to it,
+ * with no allocation, no host copy and no synchronisation.
+ *  out_dev  device pointer to TSLB_REDUCE_VALUES doubles, written
+ *           asynchronously on `stream`: mass, momentum (3), kinetic energy,
+ *           the count of fluid nodes holding NaN/Inf moments (as a double;
+ *           this call does not return TSLB_E_UNSTABLE) and the wall-shear
+ *           objective of tslb_objective.
+ * The per-block partial sums go to one fixed library array per GPU
+ * (TSLB_NOALLOC_REDUCE_BLOCKS x 7 doubles = 56 KiB, held until the process
+ * ends; every partial is rewritten by each call).  Calls that overlap on one
+ * GPU (other streams or threads) race on that array: serialise them.
+ * Errors: TSLB_E_INVALID (NULL handle or out_dev; a reduction wider than the
+ * fixed array), TSLB_E_HIP.                                                  */
+#define TSLB_REDUCE_VALUES 7
+#define TSLB_NOALLOC_REDUCE_BLOCKS 1024
+int tslb_reduce_noalloc(tslb_handle h, double *out_dev, void *stream);
+
 /* Raw state snapshots (for checkpoints and the adjoint): the state is
  * tslb_state_bytes(h) bytes of device memory holding the ten stored fields
  * in storage format, SoA, field 0 = (rho - 1) * scale[0].  dst/src are

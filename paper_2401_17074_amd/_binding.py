@@ -18,6 +18,7 @@ TSLB_PERIODIC, TSLB_WALL, TSLB_INLET, TSLB_OUTLET = 0, 1, 2, 3
 TSLB_DEVICE, TSLB_RHO_DEVIATION = 1, 2
 TSLB_OBJ_KINETIC_ENERGY, TSLB_OBJ_WALL_SHEAR = 0, 1
 TSLB_STATS_PROFILE, TSLB_STATS_FIELD = 1, 2
+TSLB_REDUCE_VALUES, TSLB_NOALLOC_REDUCE_BLOCKS = 7, 1024
 TSLB_OK, TSLB_E_INVALID, TSLB_E_UNSUPPORTED, TSLB_E_NOMEM, TSLB_E_HIP, TSLB_E_UNSTABLE = 0, -1, -2, -3, -4, -5
 
 # every symbol include/tslb.h declares, with (restype, argtypes)
@@ -60,6 +61,7 @@ SIGNATURES = {
     "tslb_get_time": (_i64, [_vp]),
     "tslb_set_time": (_i, [_vp, _i64]),
     "tslb_reduce": (_i, [_vp, ctypes.POINTER(_d), _vp]),
+    "tslb_reduce_noalloc": (_i, [_vp, _vp, _vp]),
     "tslb_state_bytes": (_sz, [_vp]),
     "tslb_save_state": (_i, [_vp, _vp, _vp]),
     "tslb_load_state": (_i, [_vp, _vp, _vp]),
@@ -219,6 +221,11 @@ def tslb_reduce(h, stream=None, check=True):
     if check:
         _check(rc)
     return list(out), rc
+
+
+def tslb_reduce_noalloc(h, out, stream=None):
+    """out: a float64 CUDA tensor of at least TSLB_REDUCE_VALUES elements."""
+    _check(lib.tslb_reduce_noalloc(h, _ptr(out), _stream(stream)))
 
 
 def tslb_state_bytes(h):

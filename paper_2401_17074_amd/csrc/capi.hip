@@ -6,6 +6,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -537,6 +538,50 @@ int tslb_reduce(tslb_handle h, double out[5], void* stream) {
     HIP_TRY(hipStreamSynchronize(s));
     for (int k = 0; k < 5; ++k) out[k] = host[k];
     if (host[5] != 0.0) return fail(TSLB_E_UNSTABLE, "%.0f fluid nodes hold NaN or Inf moments", host[5]);
+    return TSLB_OK;
+}
+
+// ------------------------------------------------ allocation-free reduction
+// The per-block partials of tslb_reduce_noalloc live in this fixed device
+// array: one copy per GPU, held until the process ends.  Its name is a
+// host-side stand-in in host code, never a device address: the address of
+// each GPU's copy is looked up once per device, with that device current,
+// and kept in g_noalloc_scratch.
+static __device__ __align__(256) double scratch[kRedSums * TSLB_NOALLOC_REDUCE_BLOCKS];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_noalloc_mu;
+double* g_noalloc_scratch[kMaxDevices] = {};
+
+// Device address of this GPU's scratch array (the caller has made `dev`
+// current).
+int noalloc_scratch(int dev, double** out) {
+    if (dev < 0 || dev >= kMaxDevices) return fail(TSLB_E_INVALID, "device %d out of range", dev);
+    std::lock_guard<std::mutex> lock(g_noalloc_mu);
+    if (!g_noalloc_scratch[dev]) {
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return fail(TSLB_E_HIP, "hipGetSymbolAddress(scratch) on device %d: %s", dev, hipGetErrorString(e));
+        g_noalloc_scratch[dev] = (double*)ptr;
+    }
+    *out = g_noalloc_scratch[dev];
+    return TSLB_OK;
+}
+}  // namespace
+
+int tslb_reduce_noalloc(tslb_handle h, double* out_dev, void* stream) {
+    if (!h || !out_dev) return fail(TSLB_E_INVALID, "NULL handle or output");
+    if (h->red_blocks < 1 || h->red_blocks > TSLB_NOALLOC_REDUCE_BLOCKS)
+        return fail(TSLB_E_INVALID, "reduction over %d blocks exceeds the fixed scratch of %d blocks", h->red_blocks,
+                    TSLB_NOALLOC_REDUCE_BLOCKS);
+    DeviceGuard dg(h->device);
+    double* part = nullptr;
+    const int rc = noalloc_scratch(h->device, &part);
+    if (rc != TSLB_OK) return rc;
+    // every partial is written before it is read: nothing to clear
+    HIP_TRY(launch_reduce(h->storage, h->buf[h->cur], part, h->red_blocks, out_dev, h->p, S(stream)));
     return TSLB_OK;
 }
 

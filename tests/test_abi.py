@@ -28,7 +28,7 @@ def lib():
 
 def test_every_declared_symbol_is_exported(lib):
     names = _declared()
-    assert len(names) == 28
+    assert len(names) == 29
     for n in names:
         assert hasattr(lib, n), n
 
@@ -74,3 +74,9 @@ def test_create_rejects_bad_boundaries(lib):
     assert C.lib.tslb_create(8, 8, 8, 27, 0.8, None, ctypes.byref(bc), ctypes.byref(h)) == -1
     assert "power of two" in C.tslb_last_error()
     assert C.lib.tslb_destroy(None) == 0
+
+
+def test_noalloc_reduce_rejects_null_arguments(lib):
+    from paper_2401_17074_amd import _binding as C
+    assert C.lib.tslb_reduce_noalloc(None, None, None) == C.TSLB_E_INVALID
+    assert "NULL" in C.tslb_last_error()
