@@ -1,0 +1,116 @@
+"""Inflow/outflow ghost layers (Section 2.3, Eq. (neq_final)) with FP32,
+FP16 and BF16 moment storage, on a grid whose rows are whole 128-byte cache
+lines for 4- and 2-byte values (nx = 64).  There the update launches its
+x-ghost variant: the fluid nodes at x = 1 and x = nx - 2 also store their
+new moments into the ghost nodes beside them, and the refill pass leaves
+those nodes alone.
+
+Each of several steps from a seeded random state (not at rest) is checked
+on every fluid node against the oracle's step of the GPU's own pre-step
+state (for 16-bit storage rounded to storage, within one storage ulp plus
+the binary32 error of the field), and every ghost node against the refill
+rule applied to the GPU's new interior.  FP32 storage is also run for the
+same steps against the oracle's multi-step run."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from helpers import abs_err, from_device_state, gpu_solver, oracle_grid, rel_err, to_device_state
+
+pytestmark = pytest.mark.gpu
+
+EPS32 = float(np.finfo(np.float32).eps)
+EPS64 = float(np.finfo(np.float64).eps)
+DEFAULT_SCALES = {0: (1.0, 1.0, 1.0), 1: (2.0 ** 12, 2.0 ** 12, 2.0 ** 16), 2: (1.0, 1.0, 1.0)}
+FRAC_BITS = {1: 10, 2: 7}
+EMIN = {1: -14, 2: -126}
+STEPS = 4
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_2401_17074_amd  # noqa: F401
+    torch.cuda.set_device(0)
+
+
+def _scaled(st, sc):
+    out = np.empty_like(st)
+    out[0] = (st[0] - 1.0) * sc[0]
+    out[1:4] = st[1:4] * sc[1]
+    out[4:] = st[4:] * sc[2]
+    return out
+
+
+def _ulp(x, kind):
+    ax = np.abs(x)
+    e = np.floor(np.log2(np.where(ax > 0, ax, 1.0)))
+    e = np.maximum(e, EMIN[kind])
+    return 2.0 ** (e - FRAC_BITS[kind])
+
+
+def _bar(want_s, exact, sc, kind):
+    """One storage ulp of the expected value plus 16 binary32 ulps of the
+    field's largest magnitude (for Pi also of |u|^2), in scaled units."""
+    u2 = float((exact[1:4] ** 2).sum(axis=0).max())
+    fp32 = np.empty(10)
+    fp32[0] = 16 * EPS32 * np.abs(exact[0] - 1.0).max() * sc[0]
+    fp32[1:4] = 16 * EPS32 * np.abs(exact[1:4]).max() * sc[1]
+    fp32[4:] = 16 * EPS32 * max(np.abs(exact[4:]).max(), u2) * sc[2]
+    return _ulp(want_s, kind) * 1.0000001 + fp32.reshape((10,) + (1,) * (want_s.ndim - 1))
+
+
+def _pi_tol(want):
+    # plus the oracle's own binary64 rounding of Pi^neq = sum f c c - rho u u
+    # - rho/3 delta, a difference of terms of size 1/3 (64 eps64 ~ 1.4e-14)
+    return 32 * EPS32 * max(float(np.abs(want[1:4]).max()) ** 2, float(np.abs(want[4:]).max()),
+                            float(np.abs(want[0] - 1.0).max())) + 64 * EPS64
+
+
+@pytest.mark.parametrize("kind", [0, 1, 2])
+def test_x_ghost_variant_steps(kind):
+    # inlet disc on x = 0, outflow ghosts on the other five faces; 3 tiles
+    # in y and a ragged last z extent
+    case = W.jet_case(nx=64, ny=30, nz=27, D=8.0, steps=STEPS)
+    sc = DEFAULT_SCALES[kind]
+    G = oracle_grid(case)
+    kinds = oracle.node_kinds(G)
+    fl, gh = kinds == 0, kinds == 2
+    st0 = oracle.ghost_fill(G, W.random_state(case.shape, seed=311, u_amp=0.04, pi_amp=1e-3), 0)
+    st0 = W.to_fp32(st0) if kind == 0 else oracle.round_storage(G, st0, kind, sc)
+    s = gpu_solver(case, storage=kind)
+    s.set_state(to_device_state(st0))
+    pre = from_device_state(s.get_state())
+    assert np.array_equal(pre[:, fl], st0[:, fl])
+    for t in range(STEPS):
+        s.step(1)
+        post = from_device_state(s.get_state())
+        exact = oracle.step(G, pre, t=t)
+        if kind == 0:
+            assert abs_err(post[0], exact[0], fl) < 1e-7
+            assert rel_err(post[1:4], exact[1:4], fl) < 2e-6
+            assert abs_err(post[4:], exact[4:], fl) < _pi_tol(exact[:, fl])
+        else:
+            want_s = _scaled(oracle.round_storage(G, exact, kind, sc), sc)[:, fl]
+            diff = np.abs(_scaled(post, sc)[:, fl] - want_s)
+            assert np.all(diff <= _bar(want_s, exact[:, fl], sc, kind)), (t, diff.max())
+            assert (diff == 0).mean() >= 0.99
+        # every ghost node: the refill rule on the GPU's own new interior
+        # (copied stored values are exact; an inlet node's imposed velocity,
+        # formed in binary32, is within one storage ulp)
+        regen = oracle.ghost_fill(G, post, t + 1)
+        if kind == 0:
+            assert abs_err(post, regen, gh) < 1e-8, t
+        else:
+            regen = oracle.round_storage(G, regen, kind, sc)
+            d = np.abs(_scaled(post, sc)[:, gh] - _scaled(regen, sc)[:, gh])
+            assert np.all(d <= _ulp(_scaled(regen, sc)[:, gh], kind) * 1.0000001), t
+        pre = post
+    if kind == 0:
+        want = oracle.run(G, st0, STEPS)
+        assert rel_err(post[1:4], want[1:4], fl) < 1e-5
+        assert abs_err(post[0], want[0], fl) < 1e-6
+        assert abs_err(post[4:], want[4:], fl) < STEPS * _pi_tol(want[:, fl])
+    s.close()

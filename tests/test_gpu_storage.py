@@ -187,3 +187,44 @@ def test_precision_workload_full_size_sampled(kind):
     diff = np.abs(got_s - want_s)
     assert np.all(diff <= _bar(want_s, want, sc, kind)), diff.max()
     assert (diff == 0).mean() >= 0.99
+
+
+def test_precision_error_report_horizons():
+    """The precision workload's 64^3 laminar channel subcase at the horizons
+    it names (10, 100 and 2000 steps): FP32, FP16 and BF16 storage against
+    the pure FP64 oracle at 2048 seeded fluid nodes, whose oracle values
+    tests/golden/make_precision_ref.py wrote (the oracle alone needs minutes
+    for 2000 steps).  Max (normwise) and RMS relative errors of u and Pi are
+    printed for the record.  Bars: FP32 storage holds the 1e-5 parity bar in
+    u up to 100 steps; everything stays finite and within loose sanity
+    bounds (the 16-bit errors are reported, not pinned)."""
+    import os
+    ref = np.load(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                               "precision_ref_channel_64.npz"), allow_pickle=False)
+    idx = ref["idx"]
+    case = W.precision_subcase()
+    st0 = W.to_fp32(W.channel_state(case))
+    report = {}
+    for kind, name in ((0, "fp32"), (1, "fp16"), (2, "bf16")):
+        s = gpu_solver(case, storage=kind)
+        s.set_state(to_device_state(st0))
+        done = 0
+        for t in ref["horizons"]:
+            s.step(int(t) - done)
+            done = int(t)
+            got = from_device_state(s.get_state()).reshape(10, -1)[:, idx]
+            want = ref["moments_%d" % t]
+            du, dp = got[1:4] - want[1:4], got[4:] - want[4:]
+            report[(name, done)] = (float(np.abs(du).max() / np.abs(want[1:4]).max()),
+                                    float(np.sqrt((du ** 2).mean() / (want[1:4] ** 2).mean())),
+                                    float(np.abs(dp).max() / np.abs(want[4:]).max()),
+                                    float(np.sqrt((dp ** 2).mean() / (want[4:] ** 2).mean())))
+            assert np.all(np.isfinite(got))
+        s.close()
+    for k, v in sorted(report.items(), key=lambda kv: (kv[0][0], kv[0][1])):
+        print("precision %s step %4d: u max %.3e rms %.3e | Pi max %.3e rms %.3e" % (k + v))
+    assert report[("fp32", 10)][0] < 1e-5 and report[("fp32", 100)][0] < 1e-5
+    for t in (10, 100, 2000):
+        assert report[("fp32", t)][0] < 1e-3
+        assert report[("fp16", t)][0] < 5e-2
+        assert report[("bf16", t)][0] < 2e-1

@@ -248,3 +248,28 @@ def to_fp32(st):
     out = st.astype(np.float32).astype(np.float64)
     out[0] = 1.0 + (st[0] - 1.0).astype(np.float32).astype(np.float64)
     return out
+
+
+def gradient_directions(case, seed, count=2):
+    """Seeded probe directions for directional-derivative checks of the
+    differentiable case: `count` standard-normal fields of shape
+    (3, nz, ny, nx), one list for the force field and one for the initial
+    velocity."""
+    rng = _rng(seed)
+    shape = (3,) + case.shape
+    dg = [rng.standard_normal(shape) for _ in range(count)]
+    du = [rng.standard_normal(shape) for _ in range(count)]
+    return dg, du
+
+
+def precision_subcase():
+    """64^3 channel subcase of the precision workload (h = 31, tau = 0.5045)
+    with the body force set for a laminar centreline velocity of 0.05:
+    g = 2 nu U_c / h^2 along x, nu = (tau - 1/2) / 3."""
+    case = channel_case(nx=64, ny=64, nz=64, tau=0.5045)
+    nu = (case.tau - 0.5) / 3
+    h = case.extra["h"]
+    case.name = "channel_64_laminar"
+    case.force = (0.05 * 2 * nu / h ** 2, 0.0, 0.0)
+    case.extra["uc"] = 0.05
+    return case
