@@ -164,3 +164,42 @@ def test_wall_shear_objective_rollout_matches_oracle(kernel):
     assert _rel(gt.grad.double().cpu().numpy(), dg_or) < 1e-4
     fl = kinds == 0
     assert _rel(ut.grad.double().cpu().numpy()[:, fl], lam0_or[1:4][:, fl]) < 1e-4
+
+
+def test_differentiable_workload_full_size_vs_central_differences():
+    """The differentiable workload at its own size: 64^3 forced periodic box,
+    400 steps, checkpoint every 20 steps, through TslbRollout.  Directional
+    derivatives of the kinetic energy along two seeded directions of the
+    force field and two of the initial velocity against the oracle's FP64
+    central differences at a relative step of 1e-4
+    (tests/golden/rollout_fd_forced_periodic_64.json, written by
+    tests/golden/make_rollout_fd.py from the oracle alone): within 1e-3
+    relative; the loss itself within 1e-5."""
+    import json
+    import os
+    import torch
+    from paper_2401_17074_amd import TslbRollout
+    rec = json.load(open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                                      "rollout_fd_forced_periodic_64.json")))
+    case = W.adjoint_case()
+    assert rec["workload"] == case.name and rec["steps"] == case.steps
+    st0, g = W.adjoint_inputs(case)
+    st0 = W.to_fp32(st0)
+    g = g.astype(np.float32).astype(np.float64)
+    s = gpu_solver(case)
+    gt = torch.tensor(g, dtype=torch.float32, device="cuda", requires_grad=True)
+    ut = torch.tensor(st0[1:4], dtype=torch.float32, device="cuda", requires_grad=True)
+    L = TslbRollout.apply(gt, ut, s, case.steps, case.extra["ckpt"])
+    L.backward()
+    s.close()
+    grad_g = gt.grad.double().cpu().numpy()
+    grad_u = ut.grad.double().cpu().numpy()
+    dgs, dus = W.gradient_directions(case, rec["direction_seed"])
+    print("loss GPU %.10g oracle %.10g" % (float(L.detach()), rec["loss"]))
+    assert float(L.detach()) == pytest.approx(rec["loss"], rel=1e-5)
+    for name, grad, dirs, fds in (("g", grad_g, dgs, rec["fd_g"]), ("u0", grad_u, dus, rec["fd_u0"])):
+        for k, (d, fd) in enumerate(zip(dirs, fds)):
+            got = float((grad * d).sum())
+            print("d/d%s along direction %d: adjoint %.10g central differences %.10g (rel %.2e)"
+                  % (name, k, got, fd, abs(got - fd) / abs(fd)))
+            assert abs(got - fd) <= 1e-3 * abs(fd)
