@@ -15,7 +15,7 @@ FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++20", "-fPIC", "-Wall",
 
 def build(verbose=False, defines=()):
     """Compile and link libtslb.so (all sources in parallel).  `defines`
-    (e.g. ("TSLB_TILE_Y=10", "TSLB_PERSISTENT=0")) are build-time tuning
+    (e.g. ("TSLB_NT_STORE=0", "TSLB_WAVES_PER_EU=3")) are build-time tuning
     overrides of the tiled kernels."""
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
     obj_dir = os.path.join(ROOT, "_build")

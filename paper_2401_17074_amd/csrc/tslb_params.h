@@ -28,6 +28,10 @@ struct StepParams {
     float* wall_side;
     long long wall_off[6];
     long long wall_nodes;
+    // Work list of the tiled update (see tile::Schedule): sched_grid blocks,
+    // sched_nseg entries {tile column, z begin, z end, 0} per block.
+    const int4* sched;
+    int sched_grid, sched_nseg;
 };
 
 // Inflow description for the ghost refill (Section 2.3).

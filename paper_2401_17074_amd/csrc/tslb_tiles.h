@@ -4,6 +4,9 @@
 // velocities), slice reductions, addressing helpers and the choice of the
 // marched z-extent.
 #pragma once
+#include <algorithm>
+#include <vector>
+
 #include "tslb_internal.h"
 
 namespace tslb {
@@ -26,12 +29,6 @@ namespace tile {
 // 0: it leaves their raw sums in a side buffer for the wall fix-up launch
 #ifndef TSLB_FUSED_WALLS
 #define TSLB_FUSED_WALLS 1
-#endif
-// 1 (default): one resident block per CU walks several tiles (see TileWalk)
-// and loads the next tile's first plane while it finishes the current one;
-// 0: one block per tile
-#ifndef TSLB_PERSISTENT
-#define TSLB_PERSISTENT 1
 #endif
 constexpr int TX = TSLB_TILE_X;              // interior tile width (64: one wave per row)
 constexpr int TY = TSLB_TILE_Y;              // interior rows
@@ -67,6 +64,53 @@ enum {
 // c_x^2 c_y (27/2 A+ + 9/2 A-), c_y c_z^2 (27/2 A+ - 9/2 A-) and -9 A+ c_y.
 template <int ORDER = 3, int LAT = 27>
 __host__ __device__ inline void coefficients(const float m[10], const float g[3], float omo, float A[NK]) {
+    if constexpr (ORDER == 3 && LAT == 27) {
+        // The expansion arranged for few instructions: q_aa = 4.5 (1 - omega)
+        // Pi_aa and q_ab = 9 (1 - omega) Pi_ab carry the constants of the
+        // quadratic coefficients, v = 4.5 rho u, and the cubic and linear
+        // coefficients reuse the quadratic ones:
+        //   A_aa  = 4.5 (rho u_a^2 + P_aa) = v_a u_a + q_aa
+        //   A_ab  = 9 (rho u_a u_b + P_ab) = 2 v_a u_b + q_ab
+        //   A_aab = 27/2 (rho u_a^2 u_b + P_aa u_b + 2 P_ab u_a) = A_aa 3u_b + q_ab 3u_a
+        //   A_xyz = 27 (rho u_x u_y u_z + P_xy u_z + P_xz u_y + P_yz u_x)
+        //         = A_xy 3u_z + q_xz 3u_y + q_yz 3u_x
+        //   A_a   = rho u_a (3 - 9/2 u^2) + u_a (27/2 P_aa - 9/2 tr P) - 9 (P u)_a + 3 rho g_a
+        //         = u_a (3 rho - v.u - 4.5 tr P + A_aa) - (q_ab u_b + q_ac u_c) + 3 rho g_a
+        //   A_0   = drho - 3/2 (rho u^2 + tr P)
+        // with P = (1 - omega) Pi.
+        const float dr = m[0], rho = 1.0f + dr;
+        const float ux = m[1], uy = m[2], uz = m[3];
+        const float o45 = 4.5f * omo, o9 = 9.0f * omo;
+        const float qxx = o45 * m[4], qyy = o45 * m[5], qzz = o45 * m[6];
+        const float qxy = o9 * m[7], qxz = o9 * m[8], qyz = o9 * m[9];
+        const float r45 = 4.5f * rho;
+        const float vx = r45 * ux, vy = r45 * uy, vz = r45 * uz;
+        const float vu = fmaf(vx, ux, fmaf(vy, uy, vz * uz));  // 4.5 rho u^2
+        const float t45 = qxx + qyy + qzz;                      // 4.5 tr P
+        A[K000] = fmaf(-1.0f / 3.0f, vu + t45, dr);
+        A[K200] = fmaf(vx, ux, qxx);
+        A[K020] = fmaf(vy, uy, qyy);
+        A[K002] = fmaf(vz, uz, qzz);
+        const float wx = vx + vx, wy = vy + vy;
+        A[K110] = fmaf(wx, uy, qxy);
+        A[K101] = fmaf(wx, uz, qxz);
+        A[K011] = fmaf(wy, uz, qyz);
+        const float r3 = 3.0f * rho;
+        const float base = r3 - vu - t45;
+        A[K100] = fmaf(ux, base + A[K200], fmaf(r3, g[0], -fmaf(qxy, uy, qxz * uz)));
+        A[K010] = fmaf(uy, base + A[K020], fmaf(r3, g[1], -fmaf(qxy, ux, qyz * uz)));
+        A[K001] = fmaf(uz, base + A[K002], fmaf(r3, g[2], -fmaf(qxz, ux, qyz * uy)));
+        const float sx = 3.0f * ux, sy = 3.0f * uy, sz = 3.0f * uz;
+        A[K210] = fmaf(A[K200], sy, qxy * sx);
+        A[K201] = fmaf(A[K200], sz, qxz * sx);
+        A[K120] = fmaf(A[K020], sx, qxy * sy);
+        A[K021] = fmaf(A[K020], sz, qyz * sy);
+        A[K102] = fmaf(A[K002], sx, qxz * sz);
+        A[K012] = fmaf(A[K002], sy, qyz * sz);
+        A[K111] = fmaf(A[K110], sz, fmaf(qxz, sy, qyz * sx));
+        return;
+    }
+
     const float dr = m[0], rho = 1.0f + dr;
     const float ux = m[1], uy = m[2], uz = m[3];
     const float pxx = omo * m[4], pyy = omo * m[5], pzz = omo * m[6];
@@ -111,24 +155,6 @@ __host__ __device__ inline void coefficients(const float m[10], const float g[3]
         A[K001] = 3.0f * (rz + rho * g[2]) - 9.0f * cp;
         return;
     }
-    // The same expansion, arranged to reuse the quadratic coefficients:
-    // 27/2 (rho u_a^2 u_b + Pi_aa u_b + 2 Pi_ab u_a) = 3 K_aa u_b + 27 Pi_ab u_a,
-    // and in the linear ones the Pi_aa u_a terms of 4.5 rho u_a^3 +
-    // 27/2 Pi_aa u_a - 9 (Pi u)_a collapse into K_aa u_a.
-    const float base = 3.0f - 4.5f * u2;
-    const float t45 = 4.5f * tr;
-    A[K100] = rx * base + ux * (A[K200] - t45) - 9.0f * (pxy * uy + pxz * uz) + 3.0f * rho * g[0];
-    A[K010] = ry * base + uy * (A[K020] - t45) - 9.0f * (pxy * ux + pyz * uz) + 3.0f * rho * g[1];
-    A[K001] = rz * base + uz * (A[K002] - t45) - 9.0f * (pxz * ux + pyz * uy) + 3.0f * rho * g[2];
-    const float qxy = 27.0f * pxy, qxz = 27.0f * pxz, qyz = 27.0f * pyz;
-    const float sxx = 3.0f * A[K200], syy = 3.0f * A[K020], szz = 3.0f * A[K002];
-    A[K210] = sxx * uy + qxy * ux;
-    A[K201] = sxx * uz + qxz * ux;
-    A[K120] = syy * ux + qxy * uy;
-    A[K021] = syy * uz + qyz * uy;
-    A[K102] = szz * ux + qxz * uz;
-    A[K012] = szz * uy + qyz * uz;
-    A[K111] = 3.0f * A[K110] * uz + qxz * uy + qyz * ux;
 }
 
 // Exact scaled weight of a velocity with n0 zero components: 216 w = 4^n0
@@ -141,8 +167,9 @@ __host__ __device__ constexpr float scaled_weight(int n0) {
 
 // Values of the 2D polynomial Q(cx, cy) = sum b_ab cx^a cy^b on the 3 x 3
 // velocity grid of one cz slice, written to G[base + 3 (cy + 1) + (cx + 1)]
-// with the exact scaled weight applied.
-template <int CZ, int LAT = 27>
+// with the exact scaled weight applied (WEIGHTED), or without it for a
+// gather that applies the weights itself (add_slice with WEIGHTS).
+template <int CZ, int LAT = 27, bool WEIGHTED = true>
 __device__ __forceinline__ void eval_slice(float b00, float b10, float b01, float b20, float b02, float b11, float b21,
                                            float b12, float G[27]) {
     // along x for each power of cy
@@ -157,39 +184,46 @@ __device__ __forceinline__ void eval_slice(float b00, float b10, float b01, floa
 #pragma unroll
         for (int iy = 0; iy < 3; ++iy) {
             const int I = 9 * (CZ + 1) + 3 * iy + ix;
-            const float w = scaled_weight<LAT>((ix == 1) + (iy == 1) + (CZ == 0));
+            const float w = WEIGHTED ? scaled_weight<LAT>((ix == 1) + (iy == 1) + (CZ == 0)) : 1.0f;
             G[I] = (w == 0.0f) ? 0.0f : ((w == 1.0f) ? q[iy] : w * q[iy]);
         }
     }
 }
 
-template <int LAT = 27>
+template <int LAT = 27, bool WEIGHTED = true>
 __device__ __forceinline__ void populations(const float A[NK], float G[27]) {
-    eval_slice<0, LAT>(A[K000], A[K100], A[K010], A[K200], A[K020], A[K110], A[K210], A[K120], G);
+    eval_slice<0, LAT, WEIGHTED>(A[K000], A[K100], A[K010], A[K200], A[K020], A[K110], A[K210], A[K120], G);
     const float e00 = A[K000] + A[K002], e10 = A[K100] + A[K102], e01 = A[K010] + A[K012];
-    eval_slice<1, LAT>(e00 + A[K001], e10 + A[K101], e01 + A[K011], A[K200] + A[K201], A[K020] + A[K021],
-                       A[K110] + A[K111], A[K210], A[K120], G);
-    eval_slice<-1, LAT>(e00 - A[K001], e10 - A[K101], e01 - A[K011], A[K200] - A[K201], A[K020] - A[K021],
-                        A[K110] - A[K111], A[K210], A[K120], G);
+    eval_slice<1, LAT, WEIGHTED>(e00 + A[K001], e10 + A[K101], e01 + A[K011], A[K200] + A[K201],
+                                 A[K020] + A[K021], A[K110] + A[K111], A[K210], A[K120], G);
+    eval_slice<-1, LAT, WEIGHTED>(e00 - A[K001], e10 - A[K101], e01 - A[K011], A[K200] - A[K201],
+                                  A[K020] - A[K021], A[K110] - A[K111], A[K210], A[K120], G);
 }
 
 // Moments of one arriving cz slice F[cy+1][cx+1], added to the output plane
-// accumulator: sum F, sum F c and sum F c c with c = (cx, cy, CZ).
-template <int CZ, bool ASSIGN = false>
+// accumulator: sum F, sum F c and sum F c c with c = (cx, cy, CZ).  With
+// WEIGHTS the values arrive without their lattice weight and the D3Q27
+// weights 216 w = 4^(zero components) are applied here, as the separable
+// factor 4 of every zero component: each one becomes the constant operand
+// of a fused multiply-add that the sum needs anyway, so the weights cost
+// no instruction (and, being powers of two, change no rounding).
+template <int CZ, bool ASSIGN = false, bool WEIGHTS = false>
 __device__ __forceinline__ void add_slice(const float F[3][3], MomentSums& a) {
+    constexpr float w0 = WEIGHTS ? 4.0f : 1.0f;           // factor of a zero component
+    constexpr float wz = (WEIGHTS && CZ == 0) ? 4.0f : 1.0f;  // of this slice
     float s[3], d[3], t[3];
 #pragma unroll
     for (int r = 0; r < 3; ++r) {
         s[r] = F[r][0] + F[r][2];
         d[r] = F[r][2] - F[r][0];
-        t[r] = s[r] + F[r][1];
+        t[r] = fmaf(w0, F[r][1], s[r]);
     }
     const float m02 = t[2] + t[0];
-    const float m00 = m02 + t[1];
+    const float m00 = fmaf(w0, t[1], m02);
     const float m01 = t[2] - t[0];
-    const float m10 = d[0] + d[1] + d[2];
+    const float m10 = fmaf(w0, d[1], d[0] + d[2]);
     const float m11 = d[2] - d[0];
-    const float m20 = s[0] + s[1] + s[2];
+    const float m20 = fmaf(w0, s[1], s[0] + s[2]);
     if constexpr (ASSIGN) {
         // first contribution to a fresh output plane (only the CZ != 0 slices
         // touch all ten sums)
@@ -205,12 +239,12 @@ __device__ __forceinline__ void add_slice(const float F[3][3], MomentSums& a) {
         a.s[4] = CZ * m10;
         a.s[5] = CZ * m01;
     } else {
-        a.d += m00;
-        a.j[0] += m10;
-        a.j[1] += m01;
-        a.s[0] += m20;
-        a.s[1] += m02;
-        a.s[3] += m11;
+        a.d = fmaf(wz, m00, a.d);
+        a.j[0] = fmaf(wz, m10, a.j[0]);
+        a.j[1] = fmaf(wz, m01, a.j[1]);
+        a.s[0] = fmaf(wz, m20, a.s[0]);
+        a.s[1] = fmaf(wz, m02, a.s[1]);
+        a.s[3] = fmaf(wz, m11, a.s[3]);
         if (CZ != 0) {
             a.j[2] += CZ * m00;
             a.s[2] += m00;
@@ -352,25 +386,6 @@ FieldPtrs<typename S::T> field_ptrs(const void* in, void* out, const StepParams&
     return f;
 }
 
-// Planes per block: every block costs about (tz + 2) plane-steps and the
-// blocks run in rounds of one per CU, so pick the tz in [1, 64] that
-// minimises rounds * (tz + 2) (fewer halo planes vs. a ragged last round;
-// small grids get short z-extents so that they still fill the chip).
-inline int choose_tz(int columns, int nz, int cus) {
-    int best = 32;
-    long long best_cost = -1;
-    for (int tz = 1; tz <= 64; ++tz) {
-        const long long blocks = (long long)columns * ((nz + tz - 1) / tz);
-        const long long rounds = (blocks + cus - 1) / cus;
-        const long long cost = rounds * (tz + 2);
-        if (best_cost < 0 || cost < best_cost) {
-            best_cost = cost;
-            best = tz;
-        }
-    }
-    return best;
-}
-
 // Blocks of the tiled kernels that one CU holds at once: bounded by LDS
 // (160 KB per CU) and by the waves the register budget allows (4 SIMDs x
 // TSLB_WAVES_PER_EU waves).
@@ -380,39 +395,104 @@ constexpr int kBlocksPerCu = (163840 / kLdsBytes) < ((4 * TSLB_WAVES_PER_EU) / (
                                  : ((4 * TSLB_WAVES_PER_EU) / (NTHREADS / 64));
 static_assert(kBlocksPerCu >= 1, "a tile must fit one CU");
 
-// Consecutive block ids are dealt round-robin to the 8 XCDs.  The launch is
-// padded to a multiple of 8 blocks and block b takes tile
-// (b % 8) * (padded / 8) + b / 8, so each XCD gets a contiguous run of
-// tiles (x fastest, then y, then z: tiles that run together on one XCD are
-// neighbours sharing halo columns in its L2); padding blocks get -1.
-__device__ __forceinline__ int xcd_tile(int b, int nblk) {
-    const int per = (nblk + 7) >> 3;
-    const int t = (b & 7) * per + (b >> 3);
-    return t < nblk ? t : -1;
-}
-inline unsigned xcd_grid(int nblk) { return (unsigned)((nblk + 7) & ~7); }
-
-// The tiles one block of the update processes.  Block ids are dealt
-// round-robin to the 8 XCDs; each XCD owns a contiguous run of
-// ceil(ntiles / 8) tiles (x fastest, then y, then z) that its gridDim / 8
-// blocks walk with stride gridDim / 8, so the tiles that run together on one
-// XCD are x and y neighbours marching the same planes and the halo columns
-// and rows they read from each other are L2 hits.  With one block per tile
-// (walk_grid with TSLB_PERSISTENT 0) every block takes a single tile.  The
-// grid size must be a multiple of 8.
-struct TileWalk {
-    int hi, stride, start;
-    __device__ TileWalk(int blk, int nblk, int ntiles) {
-        const int per = (ntiles + 7) >> 3;
-        const int lo = (blk & 7) * per;
-        hi = min(lo + per, ntiles);
-        stride = nblk >> 3;
-        start = lo + (blk >> 3);
-    }
-    __device__ int first() const { return start < hi ? start : -1; }
-    __device__ int next(int t) const { return t + stride < hi ? t + stride : -1; }
+// Work list of the tiled update.  Every block of the grid marches a short
+// list of column segments (tile column, first plane, end plane); a segment
+// of L planes costs about L + 2 plane-steps (one halo plane at each end).
+// Tiles of tz planes are dealt in whole rounds, one tile per block and
+// round; round r gives XCD k a contiguous run of tiles, so the blocks of one
+// XCD march neighbouring columns in step and read each other's halo columns
+// from its L2.  The tiles left over after the last whole round are cut into
+// `split` parts along z, and the parts, part index major, are dealt in
+// rounds the same way: without that cut a grid whose tile count is not a
+// multiple of the resident blocks leaves most CUs idle in its last round.
+// The (tz, split) with the smallest largest block cost is taken.  Entry
+// b * nseg + k is segment k of block b ({column, z begin, z end, 0}; column
+// -1 ends a shorter list); block ids are dealt round-robin to the 8 XCDs.
+struct Schedule {
+    std::vector<int4> seg;
+    int grid = 0, nseg = 0, tz = 0, split = 1;
+    long long cost = 0;
 };
 
+// The schedule for one (tz, split); with build == false only its cost (the
+// largest per-block sum of L + 2 over the block's segments) and shape.
+inline Schedule schedule_for(int columns, int nz, int resident, int tz, int split, bool build) {
+    const int tiles_z = (nz + tz - 1) / tz;
+    const long long ntiles = (long long)columns * tiles_z;
+    const int nb = resident;  // a multiple of 8
+    const long long rounds = ntiles / nb;
+    std::vector<long long> cost(nb, 0);
+    std::vector<int> count(nb, 0);
+    std::vector<std::vector<int4>> lists(build ? nb : 0);
+    // item i of a round of n items: XCD i / per, slot i % per, per = n / 8
+    // rounded up, so every XCD takes a contiguous run of the round's items
+    auto deal = [&](long long i, long long n, int col, int z0, int z1) {
+        const long long per = (n + 7) / 8;
+        const long long b = 8 * (i % per) + i / per;
+        cost[b] += z1 - z0 + 2;
+        count[b] += 1;
+        if (build) lists[b].push_back(make_int4(col, z0, z1, 0));
+    };
+    auto tile = [&](long long t, int& col, int& z0, int& z1) {
+        col = (int)(t % columns);
+        z0 = (int)(t / columns) * tz;
+        z1 = std::min(z0 + tz, nz);
+    };
+    for (long long t = 0; t < rounds * nb; ++t) {
+        int col, z0, z1;
+        tile(t, col, z0, z1);
+        deal(t % nb, nb, col, z0, z1);
+    }
+    // leftover tiles, each cut into `split` parts along z (part index major)
+    const long long left = ntiles - rounds * nb;
+    const long long parts = left * split;
+    for (long long q = 0; q < parts; ++q) {
+        const long long t = rounds * nb + q % left;
+        const int k = (int)(q / left);
+        int col, z0, z1;
+        tile(t, col, z0, z1);
+        const int len = z1 - z0;
+        const int a = z0 + (int)((long long)len * k / split), e = z0 + (int)((long long)len * (k + 1) / split);
+        if (a == e) continue;  // a part of a short tile may be empty
+        const long long r0 = q / nb * nb;
+        deal(q - r0, std::min<long long>(nb, parts - r0), col, a, e);
+    }
+    Schedule s;
+    s.tz = tz;
+    s.split = split;
+    int last = -1;
+    for (int b = 0; b < nb; ++b) {
+        s.cost = std::max(s.cost, cost[b]);
+        s.nseg = std::max(s.nseg, count[b]);
+        if (count[b] > 0) last = b;
+    }
+    s.grid = (last + 8) & ~7;
+    if (build) {
+        s.seg.assign((size_t)s.grid * s.nseg, make_int4(-1, 0, 0, 0));
+        for (int b = 0; b < s.grid; ++b)
+            for (size_t k = 0; k < lists[b].size(); ++k) s.seg[(size_t)b * s.nseg + k] = lists[b][k];
+    }
+    return s;
+}
+
+inline Schedule build_schedule(int columns, int nz, int resident) {
+    int best_tz = 1, best_split = 1;
+    long long best_cost = -1;
+    int best_nseg = 0;
+    for (int tz = 1; tz <= 64 && tz <= nz; ++tz) {
+        const long long left = ((long long)columns * ((nz + tz - 1) / tz)) % resident;
+        for (int split = 1; split <= (left ? std::min(tz, 8) : 1); ++split) {
+            const Schedule s = schedule_for(columns, nz, resident, tz, split, false);
+            if (best_cost < 0 || s.cost < best_cost || (s.cost == best_cost && s.nseg < best_nseg)) {
+                best_cost = s.cost;
+                best_nseg = s.nseg;
+                best_tz = tz;
+                best_split = split;
+            }
+        }
+    }
+    return schedule_for(columns, nz, resident, best_tz, best_split, true);
+}
 
 inline int compute_units() {
     static int cus = 0;
@@ -425,16 +505,6 @@ inline int compute_units() {
     }
     return cus;
 }
-
-// Grid of the tiled update: one block per tile, or at most the blocks that
-// are resident at once (kBlocksPerCu per CU), rounded up to a multiple of 8.
-inline unsigned walk_grid(int ntiles) {
-    const unsigned all = xcd_grid(ntiles);
-    if (!TSLB_PERSISTENT) return all;
-    const unsigned resident = (unsigned)((compute_units() * kBlocksPerCu + 7) & ~7);
-    return all < resident ? all : resident;
-}
-
 
 // Reverse-mode derivative of coefficients(): given L[k] = dF/dA_k, the
 // sensitivities of F to the node's stored moments (drho, u, Pi) and to its

@@ -35,16 +35,22 @@ using namespace tile;
 // the fluid nodes next to x ghost faces also write those ghost nodes.
 template <class S, bool WALLS, bool FIELD, int ORDER, int LAT, int MODE>
 __global__ void __launch_bounds__(NTHREADS, TSLB_WAVES_PER_EU) update_tiled_kernel(const FieldPtrs<typename S::T> f, StepParams p,
-                                                                   int tiles_x, int tiles_y, int tiles_z, int TZ) {
+                                                                   int tiles_x) {
     __shared__ float lds[NSLOT][LY][LX];
+    // D3Q27: the populations travel without their weights, which the gather
+    // applies for free (add_slice); D3Q19's weights are not separable
+    constexpr bool kDeferWeights = LAT == 27;
     const Geometry& g = p.geo;
     const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
     const unsigned plane_nodes = (unsigned)nx * (unsigned)ny;
     const bool pz = (g.periodic & 4) != 0;
 
-    const TileWalk walk(blockIdx.x, gridDim.x, tiles_x * tiles_y * tiles_z);
-    int t = walk.first();
-    if (t < 0) return;  // no tile for this block (before any barrier)
+    // this block's segments (uniform loads); an empty list ends the block
+    // before any barrier
+    const int4* __restrict__ segs = p.sched + (size_t)blockIdx.x * p.sched_nseg;
+    int k = 0;
+    int4 t = segs[0];
+    if (t.x < 0) return;
 
     // thread -> LDS column (lx, ly); interior columns first, whole waves
     const int tid = threadIdx.x;
@@ -55,15 +61,23 @@ __global__ void __launch_bounds__(NTHREADS, TSLB_WAVES_PER_EU) update_tiled_kern
         lx = 1 + tid % TX;
         ly = 1 + tid / TX;
     } else {
-        const int h = tid - NINT;
-        if (h < LX) {
-            lx = h;
+        // halo columns, one kind per wave: the row below the tile (what it
+        // sends into the tile has cy = +1), the row above (cy = -1), then the
+        // four corners and the two side columns (cx = +1 on the left, -1 on
+        // the right)
+        static_assert(TX == 64 && 4 + 2 * TY <= 64 && NTHREADS == NINT + 192, "one wave per halo row");
+        const int h = tid - NINT, lane = h & 63;
+        if (h < 64) {
+            lx = 1 + lane;
             ly = 0;
-        } else if (h < 2 * LX) {
-            lx = h - LX;
+        } else if (h < 128) {
+            lx = 1 + lane;
             ly = LY - 1;
-        } else if (h < 2 * LX + 2 * TY) {
-            const int k = h - 2 * LX;
+        } else if (lane < 4) {
+            lx = (lane & 1) ? LX - 1 : 0;
+            ly = (lane & 2) ? LY - 1 : 0;
+        } else if (lane < 4 + 2 * TY) {
+            const int k = lane - 4;
             lx = (k < TY) ? 0 : LX - 1;
             ly = 1 + (k % TY);
         } else {
@@ -72,6 +86,8 @@ __global__ void __launch_bounds__(NTHREADS, TSLB_WAVES_PER_EU) update_tiled_kern
             active = false;
         }
     }
+    // halo wave kind: 1 row below, 2 row above, 3 corners and sides
+    const int hkind = interior ? 0 : (tid - NINT < 64 ? 1 : (tid - NINT < 128 ? 2 : 3));
     const bool zlo_wall = (g.lo_solid & 4) != 0, zhi_wall = (g.hi_solid & 4) != 0;
     const bool zlo_out = ((g.lo_solid | g.lo_ghost) & 4) != 0, zhi_out = ((g.hi_solid | g.hi_ghost) & 4) != 0;
 
@@ -82,16 +98,16 @@ __global__ void __launch_bounds__(NTHREADS, TSLB_WAVES_PER_EU) update_tiled_kern
         unsigned col;  // wx + nx wy
         int zs, ze;    // output planes [zs, ze)
     };
-    auto column = [&](int tile) {
+    auto column = [&](int4 sg) {
         Column c;
-        const int tx = tile % tiles_x, ty = (tile / tiles_x) % tiles_y, tz = tile / (tiles_x * tiles_y);
+        const int tx = sg.x % tiles_x, ty = sg.x / tiles_x;
         c.gx = tx * TX - 1 + lx;
         c.gy = ty * TY - 1 + ly;
         c.wx = wrap_or_clamp(c.gx, nx, g.periodic & 1);
         c.wy = wrap_or_clamp(c.gy, ny, g.periodic & 2);
         c.col = (unsigned)c.wx + (unsigned)nx * (unsigned)c.wy;
-        c.zs = tz * TZ;
-        c.ze = min(c.zs + TZ, nz);
+        c.zs = sg.y;
+        c.ze = sg.z;
         return c;
     };
 
@@ -117,10 +133,11 @@ __global__ void __launch_bounds__(NTHREADS, TSLB_WAVES_PER_EU) update_tiled_kern
     if (active) fetch(c.col, plane_index(c.zs - 1, nz, pz));
 
     for (;;) {
-        // the block's next tile: its first plane is loaded while the last
+        // the block's next segment: its first plane is loaded while the last
         // plane of this one is exchanged and gathered
-        const int tn = walk.next(t);
-        const Column cn = column(tn >= 0 ? tn : t);
+        const int4 tn4 = k + 1 < p.sched_nseg ? segs[k + 1] : make_int4(-1, 0, 0, 0);
+        const int tn = tn4.x;
+        const Column cn = column(tn >= 0 ? tn4 : t);
         const int gx = c.gx, gy = c.gy, zs = c.zs, ze = c.ze;
 
         // interior column output properties
@@ -144,6 +161,46 @@ __global__ void __launch_bounds__(NTHREADS, TSLB_WAVES_PER_EU) update_tiled_kern
         }
         const float gon = col_solid ? 0.0f : 1.0f;
         const float gacc[3] = {gon * p.force[0], gon * p.force[1], gon * p.force[2]};
+
+        // The nine populations a halo column sends into the tile, unweighted
+        // (D3Q27): with one velocity component fixed at s = +-1 (cy for the
+        // rows below and above, cx for the corners and side columns) the
+        // polynomial P(c) collapses to one in the two other components,
+        // evaluated on their 3 x 3 grid.
+        auto emit_halo = [&](const float A[NK], int kind, int hx, int hy) {
+            float T[27];
+            if (kind != 3) {
+                const float s = kind == 1 ? 1.0f : -1.0f;  // cy
+                eval_slice<0, 27, false>(fmaf(s, A[K010], A[K000] + A[K020]), fmaf(s, A[K110], A[K100] + A[K120]),
+                                         fmaf(s, A[K011], A[K001] + A[K021]), fmaf(s, A[K210], A[K200]),
+                                         fmaf(s, A[K012], A[K002]), fmaf(s, A[K111], A[K101]), A[K201], A[K102], T);
+                // T[9 + 3 (cz + 1) + (cx + 1)]
+                if (kind == 1) {
+                    Unroll<0, 27>::run([&]<int I>() {
+                        if constexpr (cy_of(I) == 1) lds[slot_of(I)][hy][hx] = T[9 + 3 * (cz_of(I) + 1) + cx_of(I) + 1];
+                    });
+                } else {
+                    Unroll<0, 27>::run([&]<int I>() {
+                        if constexpr (cy_of(I) == -1) lds[slot_of(I)][hy][hx] = T[9 + 3 * (cz_of(I) + 1) + cx_of(I) + 1];
+                    });
+                }
+            } else {
+                const float s = hx == 0 ? 1.0f : -1.0f;  // cx
+                eval_slice<0, 27, false>(fmaf(s, A[K100], A[K000] + A[K200]), fmaf(s, A[K110], A[K010] + A[K210]),
+                                         fmaf(s, A[K101], A[K001] + A[K201]), fmaf(s, A[K120], A[K020]),
+                                         fmaf(s, A[K102], A[K002]), fmaf(s, A[K111], A[K011]), A[K021], A[K012], T);
+                // T[9 + 3 (cz + 1) + (cy + 1)]
+                if (hx == 0) {
+                    Unroll<0, 27>::run([&]<int I>() {
+                        if constexpr (cx_of(I) == 1) lds[slot_of(I)][hy][hx] = T[9 + 3 * (cz_of(I) + 1) + cy_of(I) + 1];
+                    });
+                } else {
+                    Unroll<0, 27>::run([&]<int I>() {
+                        if constexpr (cx_of(I) == -1) lds[slot_of(I)][hy][hx] = T[9 + 3 * (cz_of(I) + 1) + cy_of(I) + 1];
+                    });
+                }
+            }
+        };
 
         // One plane zp: build and publish its populations from the fetched
         // values, fetch the next plane (or the next tile's first plane), add
@@ -169,7 +226,11 @@ __global__ void __launch_bounds__(NTHREADS, TSLB_WAVES_PER_EU) update_tiled_kern
                 } else {
                     coefficients<ORDER, LAT>(m, gl, omo, A);
                 }
-                populations<LAT>(A, G);
+                if (kDeferWeights && !interior) {
+                    // a halo column only publishes what enters the tile
+                    emit_halo(A, hkind, lx, ly);
+                } else {
+                populations<LAT, !kDeferWeights>(A, G);
                 if (WALLS && TSLB_FUSED_WALLS && interior && col_fluid) {
                     // half-way bounce-back in place: a fluid node next to a wall
                     // receives its own population along -c for every c whose
@@ -177,13 +238,15 @@ __global__ void __launch_bounds__(NTHREADS, TSLB_WAVES_PER_EU) update_tiled_kern
                     const bool zlo_adj = zlo_wall && zp == 1, zhi_adj = zhi_wall && zp == nz - 2;
                     if (wf != 0 || zlo_adj || zhi_adj) {
                         Unroll<0, 27>::run([&]<int I>() {
-                            if (upstream_solid<I>(wf, zlo_adj, zhi_adj)) acur.template add<I>(G[26 - I]);
+                            if (upstream_solid<I>(wf, zlo_adj, zhi_adj))
+                                acur.template add<I>(kDeferWeights ? w216_of(I) * G[26 - I] : G[26 - I]);
                         });
                     }
                 }
                 Unroll<0, 27>::run([&]<int I>() {
                     if constexpr (cx_of(I) != 0 || cy_of(I) != 0) lds[slot_of(I)][ly][lx] = G[I];
                 });
+                }
                 // the fetched values are dead once the coefficients are
                 // formed: the next plane's go into the same registers and are
                 // in flight across the exchange, the gather and the stores
@@ -213,17 +276,17 @@ __global__ void __launch_bounds__(NTHREADS, TSLB_WAVES_PER_EU) update_tiled_kern
             constexpr bool kSumFirst = sizeof(typename S::T) == 2;
             if constexpr (kSumFirst) {
                 if (interior) {
-                    add_slice<-1>(F[0], aprev);
-                    add_slice<0>(F[1], acur);
-                    add_slice<1, true>(F[2], anext);
+                    add_slice<-1, false, kDeferWeights>(F[0], aprev);
+                    add_slice<0, false, kDeferWeights>(F[1], acur);
+                    add_slice<1, true, kDeferWeights>(F[2], anext);
                 }
             }
             __syncthreads();
             if constexpr (!kSumFirst) {
                 if (interior) {
-                    add_slice<-1>(F[0], aprev);
-                    add_slice<0>(F[1], acur);
-                    add_slice<1, true>(F[2], anext);
+                    add_slice<-1, false, kDeferWeights>(F[0], aprev);
+                    add_slice<0, false, kDeferWeights>(F[1], acur);
+                    add_slice<1, true, kDeferWeights>(F[2], anext);
                 }
             }
             const int zo = zp - 1;
@@ -286,7 +349,8 @@ __global__ void __launch_bounds__(NTHREADS, TSLB_WAVES_PER_EU) update_tiled_kern
             plane(zp + 2, a2, a0, a1);
         }
         if (tn < 0) break;
-        t = tn;
+        ++k;
+        t = tn4;
         c = cn;
     }
 }
@@ -361,28 +425,22 @@ inline bool x_ghost_faces(const StepParams& p) { return ((p.geo.lo_ghost | p.geo
 template <class S, bool WALLS, bool FIELD, int ORDER, int LAT>
 hipError_t launch_t(const void* in, void* out, const StepParams& p, hipStream_t s) {
     const int tiles_x = (p.geo.n[0] + TX - 1) / TX;
-    const int tiles_y = (p.geo.n[1] + TY - 1) / TY;
-    const int TZ = choose_tz(tiles_x * tiles_y, p.geo.n[2], compute_units() * kBlocksPerCu);
-    const int tiles_z = (p.geo.n[2] + TZ - 1) / TZ;
-    const unsigned nblk = (unsigned)tiles_x * tiles_y * tiles_z;
     if (p.geo.N >= (1LL << 30)) return hipErrorInvalidValue;  // 32-bit node offsets
+    if (!p.sched || p.sched_grid < 8 || p.sched_nseg < 1) return hipErrorInvalidValue;
     const FieldPtrs<typename S::T> f = field_ptrs<S>(in, out, p);
     // non-temporal output stores only when every row starts on a cache line
     const bool nt = rows_whole_lines<S>(p);
-    const dim3 grid(walk_grid(nblk)), block(NTHREADS);
+    const dim3 grid(p.sched_grid), block(NTHREADS);
     if constexpr (!WALLS && !FIELD) {
         if (nt && x_ghost_faces(p)) {
-            hipLaunchKernelGGL((update_tiled_kernel<S, false, false, ORDER, LAT, 2>), grid, block, 0, s, f, p, tiles_x,
-                               tiles_y, tiles_z, TZ);
+            hipLaunchKernelGGL((update_tiled_kernel<S, false, false, ORDER, LAT, 2>), grid, block, 0, s, f, p, tiles_x);
             return hipGetLastError();
         }
     }
     if (nt)
-        hipLaunchKernelGGL((update_tiled_kernel<S, WALLS, FIELD, ORDER, LAT, 1>), grid, block, 0, s, f, p, tiles_x,
-                           tiles_y, tiles_z, TZ);
+        hipLaunchKernelGGL((update_tiled_kernel<S, WALLS, FIELD, ORDER, LAT, 1>), grid, block, 0, s, f, p, tiles_x);
     else
-        hipLaunchKernelGGL((update_tiled_kernel<S, WALLS, FIELD, ORDER, LAT, 0>), grid, block, 0, s, f, p, tiles_x,
-                           tiles_y, tiles_z, TZ);
+        hipLaunchKernelGGL((update_tiled_kernel<S, WALLS, FIELD, ORDER, LAT, 0>), grid, block, 0, s, f, p, tiles_x);
     return hipGetLastError();
 }
 
@@ -429,6 +487,17 @@ hipError_t fixup_s(const void* in, void* out, const StepParams& p, hipStream_t s
 }
 
 bool tiled_uses_wall_side() { return TSLB_FUSED_WALLS == 0; }
+
+hipError_t tiled_schedule(const Geometry& g, std::vector<int4>& seg, int& grid, int& nseg) {
+    const int columns = ((g.n[0] + TX - 1) / TX) * ((g.n[1] + TY - 1) / TY);
+    const int resident = (compute_units() * kBlocksPerCu + 7) & ~7;
+    Schedule s = build_schedule(columns, g.n[2], resident);
+    if (s.grid < 8 || s.nseg < 1) return hipErrorInvalidValue;
+    seg = std::move(s.seg);
+    grid = s.grid;
+    nseg = s.nseg;
+    return hipSuccess;
+}
 
 bool tiled_writes_x_ghosts(int storage, const StepParams& p) {
     const bool walls = (p.geo.lo_solid | p.geo.hi_solid) != 0;
