@@ -1,17 +1,20 @@
 """Benchmark of the moment-only high-order TSLB update on one MI355X.
 
-Workload (the timed `value`): the channel-shaped flow, D3Q27, 384 x 192 x 192
-nodes (x, z periodic; bounce-back walls at y = 0 and y = ny - 1), friction
-Reynolds number 180 forcing, tau = 0.5045, FP32 moments, seeded synthetic
-initial state (parabolic profile + 5 % uniform perturbations).  One step is
-one full update of every node (the paper's lattice-update count, Section 4).
+Workload (the timed `value`): the precision workload's channel, D3Q27,
+512 x 256 x 256 nodes (x, z periodic; bounce-back walls at y = 0 and
+y = ny - 1), friction Reynolds number 180 forcing, tau = 0.5045, FP32
+moments, seeded synthetic initial state (parabolic profile + 5 % uniform
+perturbations).  One step is one full update of every node (the paper's
+lattice-update count, Section 4).
 
 Printed: ONE JSON line with MLUPS, the HBM roofline of the update kernel
-(algorithmic bytes per launch / measured average launch time), the FP64 CPU
-oracle timed on the host cores on a bounded sample of the same workload, and
-side measurements named by the metric: FP16/BF16-moment storage on the
-512 x 256 x 256 channel, and the adjoint-to-forward time ratio on the
-64^3 forced periodic box with checkpoints every 20 steps.
+(algorithmic bytes per launch / measured average launch time, against the
+8 TB/s peak and against the library's streaming copy measured in the same
+run), the FP64 CPU oracle timed on the host cores on bounded samples, and
+the side measurements the metric names: FP16/BF16-moment storage on the same
+channel (each with its own kernel roofline), and the adjoint-to-forward time
+ratio with checkpoints every 20 steps, on the 64^3 differentiable box and on
+a 256^3 box where bytes rather than launches dominate.
 """
 import argparse
 import hashlib
@@ -94,40 +97,71 @@ def _device_state(st64):
     return dev
 
 
-def measure_storage_variants(steps, warmup, kernel):
-    import workloads as W
-    case = W.channel_case(nx=512, ny=256, nz=256)
-    st = _device_state(W.channel_state(case))
+def kernel_roofline(case, storage, kms_per_launch, kname, copy_gbs):
+    """Roofline figures of one update launch: algorithmic bytes / launch time
+    against the 8 TB/s peak and the same-run streaming copy, and the counted
+    HBM bytes per launch when a counter summary of these sources exists."""
+    algo = algorithmic_bytes(case, storage)
+    achieved = algo / (kms_per_launch * 1e-3) / 1e9
+    rec = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": load_traffic(kname, case.name, storage),
+           "algorithmic_bytes_per_launch": algo, "avg_launch_ms": round(kms_per_launch, 5), "kernel": kname}
+    if copy_gbs:
+        rec["copy_gbs"] = round(copy_gbs, 1)
+        rec["frac_of_copy"] = round(achieved / copy_gbs, 4)
+    if rec["traffic"]:
+        rec["traffic_over_algorithmic"] = round(rec["traffic"] / algo, 4)
+    return rec
+
+
+def measure_storage_variants(case, st, steps, warmup, kernel, copy_gbs, timed=None):
+    """FP32 / FP16 / BF16 moment storage on the same workload: whole-step
+    MLUPS and each storage's own update-kernel roofline.  `timed` reuses an
+    already measured (mlups, kernel ms) pair for one storage."""
+    kname = ("update_tiled", "update_direct", "push")[kernel]
     out = {}
     for storage, name in ((0, "fp32"), (1, "fp16"), (2, "bf16")):
-        s = _solver(case, storage, kernel)
-        s.set_state(st)
-        ms, _ = time_steps(s, steps, warmup)
-        s.close()
-        mlups = case.nodes * steps / (ms * 1e-3) / 1e6
-        gbs = algorithmic_bytes(case, storage) * steps / (ms * 1e-3) / 1e9
-        out[name] = {"mlups": round(mlups, 1), "hbm_gbs": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
+        if timed and storage in timed:
+            mlups, kms = timed[storage]
+        else:
+            s = _solver(case, storage, kernel)
+            s.set_state(st)
+            ms, _ = time_steps(s, steps, warmup)
+            kms, _ = s.step_timed(min(steps, 200))
+            kms /= min(steps, 200)
+            s.close()
+            mlups = case.nodes * steps / (ms * 1e-3) / 1e6
+        out[name] = {"mlups": round(mlups, 1), "kernel_ms": round(kms, 5),
+                     "roofline": kernel_roofline(case, storage, kms, kname, copy_gbs)}
+    for name in ("fp16", "bf16"):
+        out[name]["mlups_over_fp32"] = round(out[name]["mlups"] / out["fp32"]["mlups"], 3)
     return {"workload": case.name, "steps": steps, **out}
 
 
-def measure_adjoint(kernel):
+def measure_adjoint(kernel, n=64, nsteps=None):
+    """Checkpointed rollout (every 20 steps) on an n^3 forced periodic box:
+    forward and backward-with-recompute wall time, and one adjoint step
+    against one update step (kernel only, event timed)."""
     import numpy as np
     import torch
     import workloads as W
     from paper_2401_17074_amd import capi as C
-    case = W.adjoint_case()
+    case = W.adjoint_case(n=n) if nsteps is None else W.adjoint_case(n=n, steps=nsteps)
     st, g = W.adjoint_inputs(case)
     s = _solver(case, 0, kernel)
     s.set_force_field(g.astype(np.float32))
     s.set_state(_device_state(st))
+    del st, g
     nsteps, every = case.steps, case.extra["ckpt"]
     ws = torch.empty(C.tslb_rollout_workspace_bytes(s.h, nsteps, every), dtype=torch.uint8, device="cuda")
+    init = s.save_raw()
     # warm up both directions once
     C.tslb_rollout_forward(s.h, nsteps, every, ws)
     lam = s.adjoint_seed(s.save_raw())
     dg = torch.zeros((3,) + case.shape, dtype=torch.float32, device="cuda")
     C.tslb_rollout_backward(s.h, nsteps, every, ws, lam, dg)
-    s.set_state(_device_state(st))
+    s.load_raw(init)
+    s.t = 0
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     C.tslb_rollout_forward(s.h, nsteps, every, ws)
@@ -140,6 +174,7 @@ def measure_adjoint(kernel):
     C.tslb_rollout_backward(s.h, nsteps, every, ws, lam, dg)
     torch.cuda.synchronize()
     t_bwd = time.perf_counter() - t0
+    del ws
     # kernel-only: one adjoint step vs one forward step, event timed
     raw0 = s.save_raw()
     s.step(1)
@@ -158,32 +193,47 @@ def measure_adjoint(kernel):
     s.close()
     k_adj = e[0].elapsed_time(e[1]) / reps
     k_fwd = e[2].elapsed_time(e[3]) / reps
+    del raw0, raw1, lam, lam_out, dg, init
+    torch.cuda.empty_cache()
     return {"workload": case.name, "steps": nsteps, "checkpoint_every": every,
             "forward_ms_per_step": round(t_fwd * 1e3 / nsteps, 4),
             "backward_ms_per_step": round(t_bwd * 1e3 / nsteps, 4),
             "adjoint_over_forward": round(t_bwd / t_fwd, 3),
+            "adjoint_kernel_ms": round(k_adj, 5), "update_kernel_ms": round(k_fwd, 5),
             "adjoint_kernel_over_update_kernel": round(k_adj / k_fwd, 3)}
 
 
-def copy_rate_gbs(mib=1024, reps=20):
-    """Bytes moved per second (read + write) by the runtime's device-to-device
-    copy of `mib` MiB: the practical ceiling of a read+write stream."""
+def copy_rates_gbs(mib=1024, reps=20):
+    """Bytes moved per second (read + write) by two plain device copies of
+    `mib` MiB: the library's streaming copy kernel and the runtime's own
+    device-to-device copy.  The faster is the practical ceiling of a
+    read+write stream that the update's rate is compared with."""
     import torch
+    from paper_2401_17074_amd import capi as C
     n = mib * (1 << 20) // 4
-    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    a = torch.rand(n, dtype=torch.float32, device="cuda")
     b = torch.empty_like(a)
-    b.copy_(a)
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(reps):
-        b.copy_(a)
-    e1.record()
-    torch.cuda.synchronize()
-    rate = 2.0 * n * 4 * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+
+    def rate(fn):
+        fn()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return 2.0 * n * 4 * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+
+    lib = rate(lambda: C.tslb_stream_copy(b, a))
+    ok = bool(torch.equal(a, b))
+    rt = rate(lambda: b.copy_(a))
     del a, b
     torch.cuda.empty_cache()
-    return rate
+    if not ok:
+        raise RuntimeError("streaming copy produced a wrong result")
+    return {"library_stream_copy": round(lib, 1), "runtime_copy": round(rt, 1)}
 
 
 def fluid_nodes(case):
@@ -196,10 +246,10 @@ def fluid_nodes(case):
     return count
 
 
-def cpu_baseline(case, st64, seconds_budget=12.0):
-    """The FP64 oracle as it stands, on the host cores: single-step updates of a
-    contiguous block of z-planes of the same channel state, repeated until
-    about seconds_budget of CPU time has been spent."""
+def _oracle_block_rate(case, st64, seconds_budget):
+    """The FP64 oracle as it stands: single-step updates of a contiguous block
+    of z-planes of the state, repeated until about seconds_budget of wall
+    time; returns (MLUPS, description)."""
     import numpy as np
     import oracle
     G = oracle.make_grid(case.nx, case.ny, case.nz, case.tau, faces=case.faces, force=case.force)
@@ -222,10 +272,85 @@ def cpu_baseline(case, st64, seconds_budget=12.0):
         dt = time.perf_counter() - t0
         if dt >= 0.8 * seconds_budget or reps >= 100:
             break
-    return {"value": round(reps * idx.size / dt / 1e6, 4), "unit": "MLUPS", "cores": oracle.num_threads(),
-            "kind": "oracle",
-            "sample": "%d x one FP64 update of %d fluid nodes (%d z-planes) of the %s initial state, %.1f s"
-                      % (reps, idx.size, nplanes, case.name, dt)}
+    return reps * idx.size / dt / 1e6, ("%d x one FP64 update of %d fluid nodes (%d z-planes) of the %s initial state, "
+                                         "%.1f s" % (reps, idx.size, nplanes, case.name, dt))
+
+
+def oracle_sample(kind):
+    """One bounded oracle timing, run in a child process (no GPU use) so that
+    its OpenMP thread count can be set through the environment."""
+    import numpy as np
+    import oracle
+    import workloads as W
+    if kind == "single_core":
+        case = W.channel_case(nx=512, ny=256, nz=6)
+        rate, desc = _oracle_block_rate(case, W.channel_state(case), 5.0)
+        return {"value": round(rate, 4), "unit": "MLUPS", "threads": oracle.num_threads(), "sample": desc}
+    if kind == "tgv32":
+        case = W.tgv_case()
+        G = oracle.make_grid(case.nx, case.ny, case.nz, case.tau)
+        st = W.tgv_state(case.nx, case.extra["u0"])
+        t0 = time.perf_counter()
+        oracle.run(G, st, case.steps)
+        dt = time.perf_counter() - t0
+        return {"value": round(case.nodes * case.steps / dt / 1e6, 4), "unit": "MLUPS", "seconds": round(dt, 2),
+                "threads": oracle.num_threads(), "sample": "the whole run: 32^3 Taylor-Green, 100 FP64 steps"}
+    if kind == "adjoint64":
+        case = W.adjoint_case()
+        st, g = W.adjoint_inputs(case)
+        G = oracle.make_grid(case.nx, case.ny, case.nz, case.tau)
+        t0 = time.perf_counter()
+        st1 = oracle.step(G, st, g)
+        t_f = time.perf_counter() - t0
+        lam = oracle.ke_seed(G, st1)[1]
+        t0 = time.perf_counter()
+        oracle.adjoint_step(G, st, lam, g)
+        t_a = time.perf_counter() - t0
+        n, k = case.steps, case.extra["ckpt"]
+        return {"forward_s_per_step": round(t_f, 3), "adjoint_s_per_step": round(t_a, 3),
+                "rollout_s_extrapolated": round(n * t_f + n * (t_f + t_a), 1), "threads": oracle.num_threads(),
+                "sample": "one FP64 step and one FP64 adjoint step of the 64^3 differentiable box; the %d-step "
+                          "rollout with checkpoints every %d (forward, recompute, adjoint) extrapolated from them"
+                          % (n, k)}
+    raise ValueError(kind)
+
+
+def _child_sample(kind, threads=None):
+    import subprocess
+    env = dict(os.environ)
+    if threads:
+        env["OMP_NUM_THREADS"] = str(threads)
+    r = subprocess.run([sys.executable, os.path.abspath(__file__), "--oracle-sample", kind], capture_output=True,
+                       text=True, env=env, timeout=300)
+    if r.returncode != 0:
+        return {"error": r.stderr.strip().splitlines()[-1:] or ["failed"]}
+    return json.loads(r.stdout.strip().splitlines()[-1])
+
+
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def cpu_baseline(case, st64, seconds_budget=12.0):
+    """The FP64 oracle as it stands, on the host cores: the headline value is
+    single-step updates of a block of z-planes of the timed workload's own
+    initial state on all threads; beside it the same on one thread, the
+    32^3 Taylor-Green run, and one forward and one adjoint step of the 64^3
+    differentiable box."""
+    import oracle
+    rate, desc = _oracle_block_rate(case, st64, seconds_budget)
+    return {"value": round(rate, 4), "unit": "MLUPS", "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": desc, "cpu_model": _cpu_model(), "host_cpus": os.cpu_count(),
+            "omp_num_threads_env": os.environ.get("OMP_NUM_THREADS"),
+            "single_core": _child_sample("single_core", threads=1),
+            "taylor_green_32_100_steps": _child_sample("tgv32"),
+            "adjoint_64": _child_sample("adjoint64")}
 
 
 STORAGE_NAMES = ("fp32", "fp16", "bf16")
@@ -268,14 +393,14 @@ def _counter_mean(folder, counter, name_part):
 def summarize_pmc(args):
     """HBM bytes per launch of the update kernel from FETCH_SIZE / WRITE_SIZE
     (KiB per dispatch), each scaled by what the same counter reads for a plain
-    copy of known size (bench.py --copy-calibration, 1 GiB read + 1 GiB written
-    per launch)."""
+    copy of known size (bench.py --copy-calibration 1024: the library's streaming
+    copy kernel, 1 GiB read + 1 GiB written per launch)."""
     fdir, wdir, cfdir, cwdir = args.summarize_pmc
     kname = ("update_tiled", "update_direct", "push")[args.kernel]
     fetch, nf = _counter_mean(fdir, "FETCH_SIZE", kname + "_kernel")
     write, nw = _counter_mean(wdir, "WRITE_SIZE", kname + "_kernel")
-    cfetch, _ = _counter_mean(cfdir, "FETCH_SIZE", "copyBuffer")
-    cwrite, _ = _counter_mean(cwdir, "WRITE_SIZE", "copyBuffer")
+    cfetch, _ = _counter_mean(cfdir, "FETCH_SIZE", "stream_copy_kernel")
+    cwrite, _ = _counter_mean(cwdir, "WRITE_SIZE", "stream_copy_kernel")
     copy_kib = 1024.0 * 1024.0  # 1 GiB each way
     ffac, wfac = copy_kib / cfetch, copy_kib / cwrite
     import workloads as W
@@ -389,8 +514,8 @@ def main():
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--kernel", type=int, default=0, help="0 tiled (default), 1 direct, 2 population layout")
-    ap.add_argument("--workload", default="channel", choices=sorted(WORKLOADS),
-                    help="timed workload (default: the 384x192x192 channel)")
+    ap.add_argument("--workload", default="channel512", choices=sorted(WORKLOADS),
+                    help="timed workload (default: the 512x256x256 channel of the precision workload)")
     ap.add_argument("--quick", action="store_true", help="only the timed workload (for profiling)")
     ap.add_argument("--order", type=int, default=3, choices=(2, 3),
                     help="Hermite order of the timed workload (2: the regularised collision, for profiling)")
@@ -398,36 +523,42 @@ def main():
     ap.add_argument("--storage", type=int, default=0, choices=(0, 1, 2),
                     help="moment storage of the timed workload: 0 FP32 (default), 1 FP16, 2 BF16")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
-                    help="only run a plain device copy of MIB MiB 20 times (HBM counter calibration)")
+                    help="only run the library's streaming copy of MIB MiB 20 times (HBM counter calibration)")
     ap.add_argument("--summarize-pmc", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "COPY_FETCH_DIR", "COPY_WRITE_DIR"),
                     help="turn four rocprofv3 --pmc output folders into profiles/pmc_<kernel>_<workload>.json")
+    ap.add_argument("--oracle-sample", choices=("single_core", "tgv32", "adjoint64"),
+                    help="(internal) time one bounded oracle sample on the host and print it as JSON")
     args = ap.parse_args()
+    if args.oracle_sample:
+        print(json.dumps(oracle_sample(args.oracle_sample)))
+        return
     if args.summarize_pmc:
         summarize_pmc(args)
-        return
-    if args.copy_calibration:
-        import torch
-        n = args.copy_calibration * (1 << 20) // 4
-        a = torch.ones(n, dtype=torch.float32, device="cuda")
-        b = torch.empty_like(a)
-        for _ in range(20):
-            b.copy_(a)
-        torch.cuda.synchronize()
-        print(json.dumps({"copy_bytes_per_launch": 2 * n * 4, "launches": 20}))
         return
     if args.gpus != 1:
         print("bench.py measures one GPU: the library runs the update on a single MI355X and has no "
               "multi-GPU path (--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
+    if args.copy_calibration:
+        import torch
+        from paper_2401_17074_amd import capi as C
+        n = args.copy_calibration * (1 << 20) // 4
+        a = torch.ones(n, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(20):
+            C.tslb_stream_copy(b, a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_per_launch": 2 * n * 4, "launches": 20}))
+        return
 
-    import numpy as np
     import torch
     import workloads as W
     torch.cuda.set_device(0)
 
     case, st64 = WORKLOADS[args.workload](W)
+    st_dev = _device_state(st64)
     s = _solver(case, args.storage, args.kernel, args.order)
-    s.set_state(_device_state(st64))
+    s.set_state(st_dev)
     ms, wall = time_steps(s, args.steps, args.warmup)
     # the dominant kernel alone: HIP events around each of its launches, on
     # the stream it runs on (the library's; the default stream here)
@@ -436,11 +567,12 @@ def main():
     _, rc = s.reduce(check=False)
     s.close()
     mlups = case.nodes * args.steps / (ms * 1e-3) / 1e6
-    copy_gbs = copy_rate_gbs()
+    copies = copy_rates_gbs()
+    copy_gbs = max(copies.values())
     kname = "update_d2q9" if case.lattice == 9 else ("update_tiled", "update_direct", "push")[args.kernel]
-    per_launch_s = kms * 1e-3 / n_timed
-    algo = algorithmic_bytes(case, args.storage)
-    achieved = algo / per_launch_s / 1e9
+    roof = kernel_roofline(case, args.storage, kms / n_timed, kname, copy_gbs)
+    roof["aux_ms_per_step"] = round(aux_ms / n_timed, 5)
+    roof["copy_rates_gbs"] = copies
     rec = {
         "metric": "MLUPS and % of HBM roofline (FP32 vs FP16-moment); adjoint step time / forward",
         "value": round(mlups, 1),
@@ -459,22 +591,22 @@ def main():
                    "storage": STORAGE_NAMES[args.storage], "faces": list(case.faces), "kernel": kname, "order": args.order,
                    "stable": rc == 0},
         "fluid_mlups": round(fluid_nodes(case) * args.steps / (ms * 1e-3) / 1e6, 1),
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": load_traffic(kname, case.name, args.storage),
-                     "algorithmic_bytes_per_launch": algo, "avg_launch_ms": round(per_launch_s * 1e3, 5),
-                     "kernel": kname, "aux_ms_per_step": round(aux_ms / n_timed, 5),
-                     "copy_gbs": round(copy_gbs, 1), "frac_of_copy": round(achieved / copy_gbs, 4)},
+        "roofline": roof,
         "wall_s": round(wall, 3),
     }
     if not args.quick:
-        rec["storage_variants"] = measure_storage_variants(200, 10, args.kernel)
-        rec["order_variants"] = measure_order_variants(case, _device_state(st64), 200, 10, args.kernel)
-        rec["layout_variants"] = measure_layout_variants(case, _device_state(st64), 200, 10)
-        rec["other_workloads"] = measure_workloads(["cube512", "jet", "paper_jet", "channel2d", "channel_d3q19"], 100, 5,
-                                                   args.kernel)
-        rec["statistics"] = measure_stats_cost(case, _device_state(st64), 50)
+        timed = {args.storage: (mlups, kms / n_timed)} if args.order == 3 and case.lattice == 27 else None
+        rec["storage_variants"] = measure_storage_variants(case, st_dev, 200, 10, args.kernel, copy_gbs, timed)
+        del st_dev
+        ch, ch_st = WORKLOADS["channel"](W)
+        rec["order_variants"] = measure_order_variants(ch, _device_state(ch_st), 200, 10, args.kernel)
+        rec["layout_variants"] = measure_layout_variants(ch, _device_state(ch_st), 200, 10)
+        rec["statistics"] = measure_stats_cost(ch, _device_state(ch_st), 50)
+        del ch_st
+        rec["other_workloads"] = measure_workloads(["channel", "cube512", "jet", "paper_jet", "channel2d",
+                                                    "channel_d3q19"], 100, 5, args.kernel)
         rec["adjoint"] = measure_adjoint(args.kernel)
+        rec["adjoint_256"] = measure_adjoint(args.kernel, n=256, nsteps=100)
         if not args.no_cpu:
             rec["cpu_baseline"] = cpu_baseline(case, st64)
     print(json.dumps(rec), flush=True)

@@ -322,6 +322,15 @@ int tslb_stats_jet(tslb_handle h, int axis, const float center[2], float *uc, fl
 int tslb_set_kernel(tslb_handle h, int variant);
 
 /* Message of the last failed call on this thread ("" if none). */
+/* Bandwidth reference (not part of the method): copies `bytes` from src to
+ * dst, both device pointers on the current device, with a plain streaming
+ * kernel (each 16-byte word read once and written once), asynchronously on
+ * `stream`.  Its rate is the practical read+write ceiling that the update's
+ * rate is compared with, and its HBM counter readings calibrate the
+ * counters.  Errors: TSLB_E_INVALID (NULL, overlapping buffers, a size or
+ * address that is not a multiple of 16), TSLB_E_HIP.                        */
+int tslb_stream_copy(void *dst, const void *src, size_t bytes, void *stream);
+
 const char *tslb_last_error(void);
 
 #ifdef __cplusplus

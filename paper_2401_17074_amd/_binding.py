@@ -71,11 +71,16 @@ SIGNATURES = {
     "tslb_rollout_forward": (_i, [_vp, _i, _i, _vp, _sz, _vp]),
     "tslb_rollout_backward": (_i, [_vp, _i, _i, _vp, _sz, _vp, _vp, _vp]),
     "tslb_set_kernel": (_i, [_vp, _i]),
+    "tslb_stream_copy": (_i, [_vp, _vp, _sz, _vp]),
     "tslb_last_error": (ctypes.c_char_p, []),
 }
 
 if not os.path.exists(LIB_PATH):
     raise ImportError("libtslb.so is not built (run __graft_entry__.build()); there is no fallback path")
+
+# torch first: it loads the HIP runtime the library then binds to, so that
+# both use one runtime instance (torch carries its own copy of it)
+import torch  # noqa: E402,F401
 
 lib = ctypes.CDLL(LIB_PATH)
 for _name, (_res, _args) in SIGNATURES.items():
@@ -226,6 +231,15 @@ def tslb_reduce(h, stream=None, check=True):
 def tslb_reduce_noalloc(h, out, stream=None):
     """out: a float64 CUDA tensor of at least TSLB_REDUCE_VALUES elements."""
     _check(lib.tslb_reduce_noalloc(h, _ptr(out), _stream(stream)))
+
+
+def tslb_stream_copy(dst, src, stream=None):
+    """Copy tensor src into tensor dst (same byte size) with the library's
+    streaming copy kernel."""
+    nbytes = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() != nbytes:
+        raise ValueError("size mismatch")
+    _check(lib.tslb_stream_copy(_ptr(dst), _ptr(src), nbytes, _stream(stream)))
 
 
 def tslb_state_bytes(h):

@@ -409,6 +409,47 @@ hipError_t launch_reduce(int storage, const void* st, double* partials, int nblo
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------- copy
+// Plain device-to-device stream of 16-byte words: every word read once and
+// written once, each block moving 4 x 256 consecutive words (four loads in
+// flight per thread), non-temporal loads and stores (nothing is re-read, so
+// nothing is worth keeping in the caches).  The fastest of the plain copies
+// measured on MI355X; its rate is the practical read+write bandwidth ceiling
+// the update's own rate is compared with.
+__global__ void __launch_bounds__(256) stream_copy_kernel(const float4* __restrict__ src, float4* __restrict__ dst,
+                                                          long long n4) {
+    const long long base = (long long)blockIdx.x * 1024 + threadIdx.x;
+    float4 v[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const long long i = base + 256 * k;
+        if (i < n4) {
+            const float* p = reinterpret_cast<const float*>(src + i);
+            v[k] = make_float4(__builtin_nontemporal_load(p), __builtin_nontemporal_load(p + 1),
+                               __builtin_nontemporal_load(p + 2), __builtin_nontemporal_load(p + 3));
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const long long i = base + 256 * k;
+        if (i < n4) {
+            float* p = reinterpret_cast<float*>(dst + i);
+            __builtin_nontemporal_store(v[k].x, p);
+            __builtin_nontemporal_store(v[k].y, p + 1);
+            __builtin_nontemporal_store(v[k].z, p + 2);
+            __builtin_nontemporal_store(v[k].w, p + 3);
+        }
+    }
+}
+
+hipError_t launch_stream_copy(const void* src, void* dst, long long n4, hipStream_t s) {
+    if (n4 <= 0) return hipSuccess;
+    const long long blocks = (n4 + 1023) / 1024;
+    if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(stream_copy_kernel, dim3((unsigned)blocks), dim3(256), 0, s, (const float4*)src, (float4*)dst, n4);
+    return hipGetLastError();
+}
+
 hipError_t launch_adjoint_seed(const float* st, float* lam, const StepParams& p, int objective, hipStream_t s) {
     const int block = 256;
     const unsigned grid = (unsigned)((p.geo.N + block - 1) / block);

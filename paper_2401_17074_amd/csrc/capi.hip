@@ -91,6 +91,16 @@ extern "C" {
 
 const char* tslb_last_error(void) { return g_err; }
 
+int tslb_stream_copy(void* dst, const void* src, size_t bytes, void* stream) {
+    if (!dst || !src) return fail(TSLB_E_INVALID, "NULL buffer");
+    if (bytes % 16 != 0 || ((uintptr_t)dst | (uintptr_t)src) % 16 != 0)
+        return fail(TSLB_E_INVALID, "bytes and both addresses must be multiples of 16");
+    const uintptr_t d = (uintptr_t)dst, a = (uintptr_t)src;
+    if (d < a + bytes && a < d + bytes) return fail(TSLB_E_INVALID, "source and destination overlap");
+    HIP_TRY(launch_stream_copy(src, dst, (long long)(bytes / 16), S(stream)));
+    return TSLB_OK;
+}
+
 int tslb_create(int nx, int ny, int nz, int lattice, float tau, const float force[3], const tslb_bc* bc,
                 tslb_handle* out) {
     if (!out) return fail(TSLB_E_INVALID, "out handle pointer is NULL");
@@ -198,6 +208,26 @@ int tslb_create(int nx, int ny, int nz, int lattice, float tau, const float forc
         tslb_destroy(h);
         return fail(TSLB_E_NOMEM, "device allocation of 2 x %zu bytes failed", bytes);
     }
+    if (lattice != TSLB_D2Q9) {
+        // work list of the tiled update for this grid and this GPU
+        std::vector<int4> seg;
+        int grid = 0, nseg = 0;
+        if (tiled_schedule(g, seg, grid, nseg) != hipSuccess) {
+            tslb_destroy(h);
+            return fail(TSLB_E_INVALID, "no work list for the tiled update of this grid");
+        }
+        if (hipMalloc((void**)&h->sched, sizeof(int4) * seg.size()) != hipSuccess) {
+            tslb_destroy(h);
+            return fail(TSLB_E_NOMEM, "device allocation of the tile work list failed");
+        }
+        if (hipMemcpy(h->sched, seg.data(), sizeof(int4) * seg.size(), hipMemcpyHostToDevice) != hipSuccess) {
+            tslb_destroy(h);
+            return fail(TSLB_E_HIP, "uploading the tile work list failed");
+        }
+        h->p.sched = h->sched;
+        h->p.sched_grid = grid;
+        h->p.sched_nseg = nseg;
+    }
     // rest state: drho = 0, u = 0, Pi = 0 in every format is all-zero bits
     if (hipMemset(h->buf[0], 0, bytes) != hipSuccess || hipMemset(h->buf[1], 0, bytes) != hipSuccess ||
         hipDeviceSynchronize() != hipSuccess) {
@@ -226,6 +256,7 @@ int tslb_destroy(tslb_handle h) {
     (void)hipFree(h->stats_prof);
     (void)hipFree(h->stats_part);
     (void)hipFree(h->stats_field);
+    (void)hipFree(h->sched);
     delete h;
     return TSLB_OK;
 }

@@ -1,6 +1,7 @@
 // Host-side context of a TSLB solver handle and the launchers each kernel
 // translation unit exports to the C-ABI layer.
 #pragma once
+#include <vector>
 #include <hip/hip_runtime.h>
 #include <stddef.h>
 #include <stdint.h>
@@ -15,6 +16,8 @@ namespace tslb {
 hipError_t launch_update_direct(int storage, const void* in, void* out, const StepParams& p, hipStream_t s);
 hipError_t launch_update_poplayout(int storage, const void* in, void* out, float* pop, const StepParams& p,
                                    hipStream_t s);
+// Work list of the tiled update for grid g (host-side, see tile::Schedule).
+hipError_t tiled_schedule(const Geometry& g, std::vector<int4>& seg, int& grid, int& nseg);
 hipError_t launch_update_tiled(int storage, const void* in, void* out, const StepParams& p, hipStream_t s);
 hipError_t launch_update_d2q9(int storage, const void* in, void* out, const StepParams& p, hipStream_t s);
 bool tiled_uses_wall_side();  // the tiled update needs the wall side buffer and the fix-up launch
@@ -46,6 +49,7 @@ hipError_t launch_unpack(int storage, const void* st, float* rho, float* u, floa
 constexpr int kRedSums = 7;
 hipError_t launch_reduce(int storage, const void* st, double* partials, int nblocks, double* out6,
                          const StepParams& p, hipStream_t s);
+hipError_t launch_stream_copy(const void* src, void* dst, long long n4, hipStream_t s);
 hipError_t launch_adjoint_seed(const float* st, float* lam, const StepParams& p, int objective, hipStream_t s);
 hipError_t launch_adjoint_step(const float* st0, const float* st1, const float* lam1, float* lam0, float* dg,
                                const StepParams& p, hipStream_t s);
@@ -82,4 +86,5 @@ struct tslb_ctx {
     int stats_prof_axis;     // axis the two buffers above are sized for (-1: none)
     double* stats_field;     // 9 N sums
     bool has_ghosts;
+    int4* sched;             // work list of the tiled update (owned)
 };

@@ -28,7 +28,7 @@ def lib():
 
 def test_every_declared_symbol_is_exported(lib):
     names = _declared()
-    assert len(names) == 29
+    assert len(names) == 30
     for n in names:
         assert hasattr(lib, n), n
 
@@ -80,3 +80,14 @@ def test_noalloc_reduce_rejects_null_arguments(lib):
     from paper_2401_17074_amd import _binding as C
     assert C.lib.tslb_reduce_noalloc(None, None, None) == C.TSLB_E_INVALID
     assert "NULL" in C.tslb_last_error()
+
+
+def test_stream_copy_rejects_bad_arguments(lib):
+    """Argument checks come before any device access (the addresses below
+    are never dereferenced)."""
+    from paper_2401_17074_amd import _binding as C
+    assert C.lib.tslb_stream_copy(None, None, 16, None) == C.TSLB_E_INVALID
+    assert C.lib.tslb_stream_copy(0x10008, 0x20000, 16, None) == C.TSLB_E_INVALID
+    assert "multiples of 16" in C.tslb_last_error()
+    assert C.lib.tslb_stream_copy(0x10000, 0x10010, 64, None) == C.TSLB_E_INVALID
+    assert "overlap" in C.tslb_last_error()
