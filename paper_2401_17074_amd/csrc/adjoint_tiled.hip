@@ -95,26 +95,56 @@ __device__ __forceinline__ void add_adj_slice(const float F[3][3], AdjSums& a) {
     }
 }
 
+
+// The adjoint runs one block per tile (on grids small enough to be bound by
+// latency, such as the 64^3 box of the gradient workload, this is faster
+// than walking the update's work list, which costs a dependent load before
+// the first address).  Planes per tile: every block costs about (tz + 2)
+// plane-steps and the blocks run in rounds of one per CU, so take the tz in
+// [1, 64] that minimises rounds x (tz + 2).
+inline int choose_tz(int columns, int nz, int cus) {
+    int best = 32;
+    long long best_cost = -1;
+    for (int tz = 1; tz <= 64; ++tz) {
+        const long long blocks = (long long)columns * ((nz + tz - 1) / tz);
+        const long long rounds = (blocks + cus - 1) / cus;
+        const long long cost = rounds * (tz + 2);
+        if (best_cost < 0 || cost < best_cost) {
+            best_cost = cost;
+            best = tz;
+        }
+    }
+    return best;
+}
+// Consecutive block ids are dealt round-robin to the 8 XCDs: block b takes
+// tile (b % 8) * ceil(nblk / 8) + b / 8, so each XCD gets a contiguous run of
+// neighbouring tiles; padding blocks (the grid is a multiple of 8) get -1.
+__device__ __forceinline__ int xcd_tile(int b, int nblk) {
+    const int per = (nblk + 7) >> 3;
+    const int t = (b & 7) * per + (b >> 3);
+    return t < nblk ? t : -1;
+}
+inline unsigned xcd_grid(int nblk) { return (unsigned)((nblk + 7) & ~7); }
+
 template <bool WALLS, bool FIELD, bool DG>
 __global__ void __launch_bounds__(NTHREADS, TSLB_WAVES_PER_EU)
     adjoint_tiled_kernel(const float* __restrict__ st0, const float* __restrict__ st1, const float* __restrict__ lam1,
-                         float* __restrict__ lam0, float* __restrict__ dg, StepParams p, int tiles_x) {
+                         float* __restrict__ lam0, float* __restrict__ dg, StepParams p, int tiles_x, int tiles_y,
+                         int tiles_z, int TZ) {
     __shared__ float lds[NSLOT][LY][LX];
     const Geometry& g = p.geo;
     const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
     const unsigned long long N = (unsigned long long)g.N;
     const unsigned plane_nodes = (unsigned)nx * (unsigned)ny;
 
-    // this block's column segments, the work list of the tiled update (the
-    // adjoint marches the same tiles); uniform across the block, so every
-    // thread passes the same barriers
-    const int4* __restrict__ segs = p.sched + (size_t)blockIdx.x * p.sched_nseg;
-    for (int seg = 0; seg < p.sched_nseg; ++seg) {
-    const int4 sg = segs[seg];
-    if (sg.x < 0) break;
-    const int tx = sg.x % tiles_x, ty = sg.x / tiles_x;
+    const int b = xcd_tile(blockIdx.x, tiles_x * tiles_y * tiles_z);
+    if (b < 0) return;  // padding block (before any barrier)
+    const int tx = b % tiles_x;
+    const int ty = (b / tiles_x) % tiles_y;
+    const int tz = b / (tiles_x * tiles_y);
     const int x0 = tx * TX, y0 = ty * TY;
-    const int zs = sg.y, ze = sg.z;
+    const int zs = tz * TZ;
+    const int ze = min(zs + TZ, nz);
 
     const int tid = threadIdx.x;
     int lx, ly;
@@ -272,17 +302,19 @@ __global__ void __launch_bounds__(NTHREADS, TSLB_WAVES_PER_EU)
         if (zp + 2 > ze) break;
         plane(zp + 2, a2, a0, a1);
     }
-    }
 }
 
 template <bool WALLS, bool FIELD, bool DG>
 hipError_t launch_t(const float* st0, const float* st1, const float* lam1, float* lam0, float* dg,
                     const StepParams& p, hipStream_t s) {
     const int tiles_x = (p.geo.n[0] + TX - 1) / TX;
+    const int tiles_y = (p.geo.n[1] + TY - 1) / TY;
+    const int TZ = choose_tz(tiles_x * tiles_y, p.geo.n[2], compute_units() * kBlocksPerCu);
+    const int tiles_z = (p.geo.n[2] + TZ - 1) / TZ;
+    const unsigned nblk = (unsigned)tiles_x * tiles_y * tiles_z;
     if (p.geo.N >= (1LL << 30)) return hipErrorInvalidValue;
-    if (!p.sched || p.sched_grid < 8 || p.sched_nseg < 1) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((adjoint_tiled_kernel<WALLS, FIELD, DG>), dim3(p.sched_grid), dim3(NTHREADS), 0, s, st0, st1,
-                       lam1, lam0, dg, p, tiles_x);
+    hipLaunchKernelGGL((adjoint_tiled_kernel<WALLS, FIELD, DG>), dim3(xcd_grid(nblk)), dim3(NTHREADS), 0, s, st0, st1, lam1,
+                       lam0, dg, p, tiles_x, tiles_y, tiles_z, TZ);
     return hipGetLastError();
 }
 
