@@ -302,7 +302,7 @@ def adjoint_step(grid, st, lam1, g=None):
     lam0 = np.empty_like(st)
     dg = np.zeros((3,) + grid.shape)
     if _load().or_adjoint_step(ctypes.byref(grid), _p(st), _p(g), _p(lam1), _p(lam0), _p(dg)) != 0:
-        raise ValueError("oracle adjoint: unsupported grid (ghost layers)")
+        raise ValueError("oracle adjoint: unsupported lattice or out of memory")
     return lam0, dg
 
 
@@ -315,7 +315,7 @@ def adjoint_nodes(grid, st, lam1, idx, g=None):
     dg = np.empty((3, idx.size))
     if _load().or_adjoint_nodes(ctypes.byref(grid), _p(st), _p(g), _p(lam1), idx.ctypes.data_as(_L), idx.size,
                                 _p(lam), _p(dg)) != 0:
-        raise ValueError("oracle adjoint: unsupported grid (ghost layers)")
+        raise ValueError("oracle adjoint: unsupported lattice or out of memory")
     return lam, dg
 
 
@@ -347,5 +347,5 @@ def rollout_grad(grid, st0, nsteps, g=None, t0=0, objective=OBJ_KINETIC_ENERGY):
     dg = np.zeros((3,) + grid.shape)
     if _load().or_rollout_grad(ctypes.byref(grid), _p(st0), _p(g), t0, nsteps, objective, ctypes.byref(loss),
                                _p(lam0), _p(dg)) != 0:
-        raise ValueError("oracle adjoint: unsupported grid (ghost layers)")
+        raise ValueError("oracle adjoint: unsupported lattice or out of memory")
     return loss.value, lam0, dg

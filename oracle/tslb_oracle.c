@@ -463,8 +463,12 @@ double or_inlet_xi(uint64_t seed, long t, long n, long N, int a) { return inlet_
 double or_inlet_gauss(uint64_t seed, long t, long n, long N, int a) { return inlet_gauss(seed, t, n, N, a); }
 
 /* ------------------------------------------------------------------ */
-/* Tangent and adjoint of one step (fluid nodes; periodic axes and walls;
- * ghost layers are not differentiated).                                   */
+/* Tangent and adjoint of one step (periodic axes, walls and inflow/outflow
+ * ghost layers).  One step maps level t to level t+1: the update of the
+ * fluid nodes from every node of level t (ghost nodes being ordinary
+ * emitters), then the ghost refill of level t+1 from the new fluid nodes
+ * (Section 2.3, Eq. (neq_final)).  Ghost values of level t are inputs of
+ * the step like any other node.                                           */
 
 /* Tangent (Jacobian-vector product) of one step by the complex step:
  * dout = d step(st, gf) [dst, dgf].                                        */
@@ -534,6 +538,30 @@ static void adjoint_emit(const or_grid *G, const double *st, const double *gf, l
     }
 }
 
+/* Transpose of the ghost refill, in place: every ghost node copied its
+ * moments from its interior neighbour (all ten, or rho and Pi^neq only on an
+ * inlet disc, whose velocity is imposed and does not depend on the state),
+ * so its sensitivities are added to that neighbour's and set to zero.
+ * Sequential, in node order (several ghosts share a neighbour).             */
+static void fold_ghost_sensitivities(const or_grid *G, double *lam)
+{
+    const long N = (long)G->nx * G->ny * G->nz;
+    if (!grid_has_ghosts(G)) return;
+    for (long n = 0; n < N; n++) {
+        if (node_kind(G, n) != NODE_GHOST) continue;
+        int x[3], xf[3];
+        double ub[3];
+        node_coords(G, n, x);
+        interior_neighbour(G, x, xf);
+        long nf = node_index(G, xf);
+        int imposed = inlet_velocity(G, x, n, 0, ub);
+        for (int q = 0; q < 10; q++) {
+            if (!(imposed && q >= 1 && q <= 3)) lam[q * N + nf] += lam[q * N + n];
+            lam[q * N + n] = 0.0;
+        }
+    }
+}
+
 /* Reverse-mode sensitivity at node y (gather from the downstream nodes):
  * lam_t(y) = sum over populations emitted by y of J^T lam_f, where y emits
  * population i to y + c_i, and, for each direction whose upstream node is
@@ -543,7 +571,8 @@ static int adjoint_node(const or_grid *G, const double *st, const double *gf, co
 {
     for (int q = 0; q < 10; q++) lm[q] = 0.0;
     for (int a = 0; a < 3; a++) lg[a] = 0.0;
-    if (node_kind(G, y) != NODE_FLUID) return 0;
+    const int kind = node_kind(G, y);
+    if (kind == NODE_SOLID) return 0; /* walls emit nothing */
     int xy[3];
     node_coords(G, y, xy);
     for (int i = 0; i < NQ; i++) {
@@ -563,7 +592,7 @@ static int adjoint_node(const or_grid *G, const double *st, const double *gf, co
                 adjoint_populations(G, st, gf, lam1, x, lf);
             adjoint_emit(G, st, gf, y, i, lf[i], lm, lg);
         }
-        if (upstream(G, xy, i) == -1) { /* bounce-back: y feeds itself */
+        if (kind == NODE_FLUID && upstream(G, xy, i) == -1) { /* bounce-back: y feeds itself */
             double lf[NQ];
             if (lf_all)
                 memcpy(lf, lf_all + (size_t)y * NQ, sizeof lf);
@@ -576,28 +605,32 @@ static int adjoint_node(const or_grid *G, const double *st, const double *gf, co
 }
 
 /* Full-grid adjoint of one step from level t: lam_t = J_M^T lam_{t+1} and
- * dg += J_g^T lam_{t+1} (dg may be NULL).  Ghost layers are unsupported.    */
+ * dg += J_g^T lam_{t+1} (dg may be NULL): the ghost refill of level t+1
+ * transposed first, then the update.                                       */
 int or_adjoint_step(const or_grid *G, const double *st, const double *gf, const double *lam1, double *lam0,
                     double *dg)
 {
     if (G->lattice != 0 && G->lattice != 27) return -3; /* derivatives: D3Q27 only */
     lattice_init();
-    if (grid_has_ghosts(G)) return -1;
     const long N = (long)G->nx * G->ny * G->nz;
     double *lf_all = (double *)calloc((size_t)N * NQ, sizeof(double));
-    if (!lf_all) return -1;
+    double *lamf = (double *)malloc(sizeof(double) * 10 * N);
+    if (!lf_all || !lamf) return -1;
+    memcpy(lamf, lam1, sizeof(double) * 10 * N);
+    fold_ghost_sensitivities(G, lamf);
 #pragma omp parallel for schedule(static)
     for (long x = 0; x < N; x++)
-        if (node_kind(G, x) == NODE_FLUID) adjoint_populations(G, st, gf, lam1, x, lf_all + (size_t)x * NQ);
+        if (node_kind(G, x) == NODE_FLUID) adjoint_populations(G, st, gf, lamf, x, lf_all + (size_t)x * NQ);
 #pragma omp parallel for schedule(static)
     for (long y = 0; y < N; y++) {
         double lm[10], lg[3];
-        adjoint_node(G, st, gf, lam1, lf_all, y, lm, lg);
+        adjoint_node(G, st, gf, lamf, lf_all, y, lm, lg);
         for (int q = 0; q < 10; q++) lam0[q * N + y] = lm[q];
         if (dg)
             for (int a = 0; a < 3; a++) dg[a * N + y] += lg[a];
     }
     free(lf_all);
+    free(lamf);
     return 0;
 }
 
@@ -607,14 +640,23 @@ int or_adjoint_nodes(const or_grid *G, const double *st, const double *gf, const
 {
     if (G->lattice != 0 && G->lattice != 27) return -3; /* derivatives: D3Q27 only */
     lattice_init();
-    if (grid_has_ghosts(G)) return -1;
+    const long N = (long)G->nx * G->ny * G->nz;
+    double *lamf = NULL;
+    if (grid_has_ghosts(G)) {
+        lamf = (double *)malloc(sizeof(double) * 10 * N);
+        if (!lamf) return -1;
+        memcpy(lamf, lam1, sizeof(double) * 10 * N);
+        fold_ghost_sensitivities(G, lamf);
+    }
+    const double *lam = lamf ? lamf : lam1;
 #pragma omp parallel for schedule(dynamic, 4)
     for (long k = 0; k < nidx; k++) {
         double lm[10], lg[3];
-        adjoint_node(G, st, gf, lam1, NULL, idx[k], lm, lg);
+        adjoint_node(G, st, gf, lam, NULL, idx[k], lm, lg);
         for (int q = 0; q < 10; q++) lam_out[q * nidx + k] = lm[q];
         for (int a = 0; a < 3; a++) dg_out[a * nidx + k] = lg[a];
     }
+    free(lamf);
     return 0;
 }
 
@@ -671,19 +713,22 @@ double or_wall_shear_seed(const or_grid *G, const double *st, double *lam)
 /* Gradient of L(state after nsteps) with respect to the initial state and the
  * force field, by storing every level and sweeping the adjoint backwards.
  * objective 0: kinetic energy (or_ke_seed); 1: wall shear (or_wall_shear_seed).
- * lam0 (10N) receives dL/dM_0; dg (3N, may be NULL) receives dL/dg.          */
+ * lam0 (10N) receives dL/dM_0; dg (3N, may be NULL) receives dL/dg.  The
+ * ghost layers of the initial state are refilled from its interior (level
+ * t0) first, so L is a function of the interior and of the force field, and
+ * lam0 is zero on ghost nodes.                                              */
 int or_rollout_grad(const or_grid *G, const double *st0, const double *gf, long t0, int nsteps, int objective,
                     double *loss, double *lam0, double *dg)
 {
     if (G->lattice != 0 && G->lattice != 27) return -3; /* derivatives: D3Q27 only */
     lattice_init();
-    if (grid_has_ghosts(G)) return -1;
     const long N = (long)G->nx * G->ny * G->nz;
     double *traj = (double *)malloc(sizeof(double) * 10 * N * (size_t)(nsteps + 1));
     double *lam = (double *)malloc(sizeof(double) * 10 * N);
     double *tmp = (double *)malloc(sizeof(double) * 10 * N);
     if (!traj || !lam || !tmp) return -1;
     memcpy(traj, st0, sizeof(double) * 10 * N);
+    ghost_fill_r(G, traj, t0);
     for (int s = 0; s < nsteps; s++)
         step_r(G, traj + (size_t)s * 10 * N, traj + (size_t)(s + 1) * 10 * N, gf, t0 + s);
     *loss = objective == 1 ? or_wall_shear_seed(G, traj + (size_t)nsteps * 10 * N, lam)
@@ -693,6 +738,7 @@ int or_rollout_grad(const or_grid *G, const double *st0, const double *gf, long 
         or_adjoint_step(G, traj + (size_t)s * 10 * N, gf, lam, tmp, dg);
         memcpy(lam, tmp, sizeof(double) * 10 * N);
     }
+    fold_ghost_sensitivities(G, lam); /* the refill of the initial level */
     memcpy(lam0, lam, sizeof(double) * 10 * N);
     free(traj);
     free(lam);

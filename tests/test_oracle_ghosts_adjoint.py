@@ -278,3 +278,82 @@ def test_wall_shear_rollout_gradient_matches_central_differences(oracle):
         h = 1e-4 * np.abs(st0[1:4]).max()
         fd = (loss(st0 + h * du, g) - loss(st0 - h * du, g)) / (2 * h)
         assert (lam0 * du).sum() == pytest.approx(fd, rel=1e-6)
+
+
+def _small_jet(oracle, noise_kind=0):
+    """7 x 6 x 5 nodes: inlet disc of radius 1.6 on x = 0, outflow ghosts on
+    every other face; tau 0.62."""
+    return oracle.make_grid(7, 6, 5, 0.62, faces=(2, 3, 3, 3, 3, 3), inlet_u=(0.04, 0.0, 0.0),
+                            inlet_center=(2.5, 2.0), inlet_radius=1.6, inlet_noise=0.02, seed=31,
+                            noise_kind=noise_kind)
+
+
+@pytest.mark.parametrize("noise_kind", [0, 1])
+def test_adjoint_dot_product_identity_with_ghost_layers(oracle, noise_kind):
+    """<lam, J v> = <J^T lam, v> + <dL/dg, dg> through inflow and outflow
+    ghost layers (Section 2.3): the tangent is the complex step of the whole
+    step (update, then the refill of the new level), the adjoint folds the
+    ghosts' sensitivities into the interior nodes they copy and treats the
+    ghost values of level t as inputs.  Every node of v and lam is random,
+    ghosts included."""
+    G = _small_jet(oracle, noise_kind)
+    kinds = oracle.node_kinds(G)
+    assert (kinds == 2).sum() > 0 and (kinds == 0).sum() > 0
+    st = oracle.ghost_fill(G, W.random_state(G.shape, seed=32, u_amp=0.04, pi_amp=1e-3), 3)
+    g = W.random_force(G.shape, seed=33, amp=1e-4)
+    rng = np.random.default_rng(34)
+    v = rng.standard_normal(st.shape)
+    dg = rng.standard_normal(g.shape)
+    lam1 = rng.standard_normal(st.shape)
+    jv = oracle.jvp_step(G, st, v, g, dg, t=3)
+    lam0, gg = oracle.adjoint_step(G, st, lam1, g)
+    lhs = (lam1 * jv).sum()
+    rhs = (lam0 * v).sum() + (gg * dg).sum()
+    assert lhs == pytest.approx(rhs, rel=1e-11)
+    # the tangent of a ghost node of level t+1 is that of the node it copies
+    # (its imposed velocity on the inlet disc has none)
+    assert np.abs(jv[:, kinds == 2]).max() > 0
+    # a ghost's sensitivity does not stay on it: lam0 at ghosts is what they
+    # feed as emitters, and nodes that emit nothing have none
+    assert np.abs(lam0[:, kinds == 2]).max() > 0
+
+
+def test_adjoint_nodes_match_full_adjoint_with_ghost_layers(oracle):
+    G = _small_jet(oracle)
+    st = oracle.ghost_fill(G, W.random_state(G.shape, seed=35), 0)
+    lam1 = np.random.default_rng(36).standard_normal(st.shape)
+    lam0, dg = oracle.adjoint_step(G, st, lam1)
+    idx = np.arange(0, G.n, 5)
+    lam_s, dg_s = oracle.adjoint_nodes(G, st, lam1, idx)
+    assert np.allclose(lam_s, lam0.reshape(10, -1)[:, idx], rtol=1e-13, atol=1e-14)
+    assert np.allclose(dg_s, dg.reshape(3, -1)[:, idx], rtol=1e-13, atol=1e-14)
+
+
+def test_rollout_gradient_with_ghost_layers_matches_central_differences(oracle):
+    """FP64 central differences of the kinetic energy after 6 steps of the
+    small jet (inlet disc with seeded noise, outflow ghosts), along random
+    directions of g and of the interior initial velocity; the initial ghost
+    layers are refilled from the interior on both sides."""
+    G = _small_jet(oracle)
+    kinds = oracle.node_kinds(G)
+    steps = 6
+    st0 = oracle.ghost_fill(G, W.random_state(G.shape, seed=37, u_amp=0.04, pi_amp=1e-3), 0)
+    g = W.random_force(G.shape, seed=38, amp=1e-3)
+    L, lam0, dgrad = oracle.rollout_grad(G, st0, steps, g)
+    assert np.abs(lam0[:, kinds == 2]).max() == 0.0
+
+    def loss(s, gf):
+        return oracle.ke_seed(G, oracle.run(G, oracle.ghost_fill(G, s, 0), steps, gf))[0]
+
+    assert L == pytest.approx(loss(st0, g), rel=1e-14)
+    rng = np.random.default_rng(39)
+    for _ in range(2):
+        d = rng.standard_normal(g.shape)
+        h = 1e-4 * np.abs(g).max()
+        fd = (loss(st0, g + h * d) - loss(st0, g - h * d)) / (2 * h)
+        assert (dgrad * d).sum() == pytest.approx(fd, rel=1e-6)
+        du = np.zeros_like(st0)
+        du[1:4][:, kinds == 0] = rng.standard_normal((3, int((kinds == 0).sum())))
+        h = 1e-4 * np.abs(st0[1:4]).max()
+        fd = (loss(st0 + h * du, g) - loss(st0 - h * du, g)) / (2 * h)
+        assert (lam0 * du).sum() == pytest.approx(fd, rel=1e-6)
