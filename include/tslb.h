@@ -233,9 +233,17 @@ int tslb_bind_state(tslb_handle h, void *buf0, void *buf1, void *stream);
  * t+1 = step(state_t).  lam_t1, lam_t: 10N floats, SoA, one sensitivity per
  * stored moment (rho, u_x, u_y, u_z, Pi xx, yy, zz, xy, xz, yz); lam_t may
  * not alias lam_t1.  Uses tau, force and faces of h.
- * Errors: TSLB_E_UNSUPPORTED unless storage is FP32 and no face is an
- * inlet/outlet (periodic and wall faces are supported).                     */
-int tslb_adjoint_step(tslb_handle h, const void *state_t, const void *state_t1, const float *lam_t1, float *lam_t,
+ * With inflow/outflow ghost layers (Section 2.3, Eq. (neq_final)) a step is
+ * the update of the fluid nodes followed by the refill of the new level's
+ * ghosts from the interior nodes they copy; the ghost values of level t are
+ * inputs like any other node (lam_t is nonzero there: ghosts emit).  The
+ * refill is transposed first, IN PLACE on lam_t1: each ghost node's
+ * sensitivities are added to the node it copies (rho and Pi^neq only on an
+ * inlet disc, whose velocity is imposed) and then cleared.  Without ghost
+ * layers lam_t1 is only read.
+ * Errors: TSLB_E_UNSUPPORTED unless storage is FP32, the order is 3 and the
+ * lattice D3Q27.                                                            */
+int tslb_adjoint_step(tslb_handle h, const void *state_t, const void *state_t1, float *lam_t1, float *lam_t,
                       float *dg_accum, void *stream);
 
 /* Seed of the adjoint: lam = dL/dM for the objective at a raw state
@@ -263,7 +271,10 @@ int tslb_objective(tslb_handle h, int objective, double *out, void *stream);
  * dg_accum (3N, may be NULL), recomputing each segment once from its
  * checkpoint (each level computed straight into the workspace) and running
  * tslb_adjoint_step backwards through it; the handle's state and level are
- * left as they were.                                                         */
+ * left as they were.  With ghost layers the recomputed levels are refilled
+ * like the forward ones, and lam on return is the gradient with respect to
+ * the initial level's interior (its ghosts were refilled from it: their
+ * sensitivities are folded in and cleared).                                  */
 size_t tslb_rollout_workspace_bytes(tslb_handle h, int nsteps, int every);
 int tslb_rollout_forward(tslb_handle h, int nsteps, int every, void *ws, size_t ws_bytes, void *stream);
 int tslb_rollout_backward(tslb_handle h, int nsteps, int every, void *ws, size_t ws_bytes, float *lam,

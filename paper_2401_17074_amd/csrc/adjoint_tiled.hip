@@ -233,7 +233,9 @@ __global__ void __launch_bounds__(NTHREADS, TSLB_WAVES_PER_EU)
             if (WALLS) {
                 // own population bounced back: a_y(c_j) arrives as if along -c_j
                 const bool zlo = zlo_wall && zp == 1, zhi = zhi_wall && zp == nz - 2;
-                if (wf != 0 || zlo || zhi) {
+                // bounce-back happens at fluid nodes only (ghost nodes are
+                // sources, never updated)
+                if ((wf != 0 || zlo || zhi) && is_fluid(g, gx, gy, zp)) {
                     auto bounce_slice = [&]<int CZ>(float (&Fb)[3][3]) {
                         Unroll<0, 9>::run([&]<int K>() {
                             constexpr int I = 9 * (CZ + 1) + K, J = 26 - I;  // J = -c_I
@@ -258,8 +260,9 @@ __global__ void __launch_bounds__(NTHREADS, TSLB_WAVES_PER_EU)
         const int zo = zp - 1;
         if (interior && zo >= zs && zo < ze && valid) {
             const unsigned on = col + plane_nodes * (unsigned)zo;
+            // every node that emits (fluid or ghost; walls emit nothing)
             const bool fl = col_fluid_any && !(zlo_wall && zo == 0) && !(zhi_wall && zo == nz - 1) &&
-                            is_fluid(g, gx, gy, zo);
+                            !is_solid(g, gx, gy, zo);
             float out[10], lg[3] = {0.0f, 0.0f, 0.0f};
             float dg_old[3] = {0.0f, 0.0f, 0.0f};  // read with the moments, not after the stores
             if (fl) {

@@ -288,11 +288,14 @@ __global__ void __launch_bounds__(256) adjoint_step_kernel(const float* __restri
     const int x = (int)(n % g.n[0]);
     const int y = (int)((n / g.n[0]) % g.n[1]);
     const int z = (int)(n / ((long long)g.n[0] * g.n[1]));
-    if (!is_fluid(g, x, y, z)) {
+    // walls emit nothing; fluid and ghost nodes emit (a ghost node is an
+    // ordinary source of the update, Section 2.3)
+    if (is_solid(g, x, y, z)) {
 #pragma unroll
         for (int k = 0; k < 10; ++k) lam0[k * g.N + n] = 0.0f;
         return;
     }
+    const bool fluid = is_fluid(g, x, y, z);
     float m[10], gg[3];
 #pragma unroll
     for (int k = 0; k < 10; ++k) m[k] = st0[k * g.N + n];
@@ -310,7 +313,8 @@ __global__ void __launch_bounds__(256) adjoint_step_kernel(const float* __restri
         if ((g.periodic >> 0) & 1) dx = dx < 0 ? dx + g.n[0] : (dx >= g.n[0] ? dx - g.n[0] : dx);
         if ((g.periodic >> 1) & 1) dy = dy < 0 ? dy + g.n[1] : (dy >= g.n[1] ? dy - g.n[1] : dy);
         if ((g.periodic >> 2) & 1) dz = dz < 0 ? dz + g.n[2] : (dz >= g.n[2] ? dz - g.n[2] : dz);
-        if (is_fluid(g, dx, dy, dz)) {
+        const bool inside = dx >= 0 && dx < g.n[0] && dy >= 0 && dy < g.n[1] && dz >= 0 && dz < g.n[2];
+        if (inside && is_fluid(g, dx, dy, dz)) {
             const long long d = dx + (long long)g.n[0] * (dy + (long long)g.n[1] * dz);
             float l[10], u1[3];
 #pragma unroll
@@ -325,7 +329,7 @@ __global__ void __launch_bounds__(256) adjoint_step_kernel(const float* __restri
         if ((g.periodic >> 0) & 1) ux = ux < 0 ? ux + g.n[0] : (ux >= g.n[0] ? ux - g.n[0] : ux);
         if ((g.periodic >> 1) & 1) uy = uy < 0 ? uy + g.n[1] : (uy >= g.n[1] ? uy - g.n[1] : uy);
         if ((g.periodic >> 2) & 1) uz = uz < 0 ? uz + g.n[2] : (uz >= g.n[2] ? uz - g.n[2] : uz);
-        if (is_solid(g, ux, uy, uz)) {
+        if (fluid && is_solid(g, ux, uy, uz)) {
             float l[10], u1[3];
 #pragma unroll
             for (int k = 0; k < 10; ++k) l[k] = lam1[k * g.N + n];
@@ -340,6 +344,72 @@ __global__ void __launch_bounds__(256) adjoint_step_kernel(const float* __restri
     if (dg)
 #pragma unroll
         for (int a = 0; a < 3; ++a) dg[a * g.N + n] += acc[10 + a];
+}
+
+// The transpose of the ghost refill, in place on a sensitivity field lam
+// (10 N floats): every ghost node copied the ten moments of its interior
+// neighbour (rho and Pi^neq only on an inlet disc, whose velocity is imposed
+// and does not depend on the state), so its sensitivities are added to that
+// neighbour's and cleared.  Threads enumerate the interior layers next to
+// the ghost faces (a node on several of them is done once, by the first);
+// each gathers, in a fixed order, from the ghost nodes among its 26
+// neighbours that copy it.  Every ghost copies exactly one node, so the
+// update in place is race free.
+__global__ void ghost_fold_kernel(float* __restrict__ lam, StepParams p, InletParams q, long long off1,
+                                  long long off2, long long off3, long long off4, long long off5, long long total) {
+    const Geometry& g = p.geo;
+    const long long tid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (tid >= total) return;
+    const long long offs[6] = {0, off1, off2, off3, off4, off5};
+    int f = 5;
+    while (f > 0 && tid < offs[f]) --f;
+    if (q.face_kind[f] != kInlet && q.face_kind[f] != kOutlet) return;
+    const int d = f >> 1;
+    const int d1 = d == 0 ? 1 : 0, d2 = d == 2 ? 1 : 2;
+    const long long local = tid - offs[f];
+    auto inner = [&](int face) { return (face & 1) ? g.n[face >> 1] - 2 : 1; };
+    int c[3];
+    c[d] = inner(f);
+    c[d1] = (int)(local % g.n[d1]);
+    c[d2] = (int)(local / g.n[d1]);
+    if (c[d2] >= g.n[d2]) return;
+    if (!is_fluid(g, c[0], c[1], c[2])) return;
+    for (int f2 = 0; f2 < f; ++f2)
+        if ((q.face_kind[f2] == kInlet || q.face_kind[f2] == kOutlet) && c[f2 >> 1] == inner(f2)) return;
+    const long long n = c[0] + (long long)g.n[0] * (c[1] + (long long)g.n[1] * c[2]);
+    float acc[10];
+#pragma unroll
+    for (int k = 0; k < 10; ++k) acc[k] = lam[k * g.N + n];
+    for (int o = 0; o < 27; ++o) {
+        const int e[3] = {c[0] + o % 3 - 1, c[1] + (o / 3) % 3 - 1, c[2] + o / 9 - 1};
+        if (o == 13 || e[0] < 0 || e[0] >= g.n[0] || e[1] < 0 || e[1] >= g.n[1] || e[2] < 0 || e[2] >= g.n[2])
+            continue;
+        bool ghost = false, src = true;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            int cf = e[a];
+            if (e[a] == 0 && ((g.lo_ghost >> a) & 1)) {
+                ghost = true;
+                cf = 1;
+            }
+            if (e[a] == g.n[a] - 1 && ((g.hi_ghost >> a) & 1)) {
+                ghost = true;
+                cf = g.n[a] - 2;
+            }
+            src &= cf == c[a];
+        }
+        if (!ghost || !src || is_solid(g, e[0], e[1], e[2])) continue;
+        const long long m = e[0] + (long long)g.n[0] * (e[1] + (long long)g.n[1] * e[2]);
+        float u[3];
+        const bool imposed = inlet_velocity(g, q, p.dims, 0, m, e, u);
+#pragma unroll
+        for (int k = 0; k < 10; ++k) {
+            if (!(imposed && k >= 1 && k <= 3)) acc[k] += lam[k * g.N + m];
+            lam[k * g.N + m] = 0.0f;
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < 10; ++k) lam[k * g.N + n] = acc[k];
 }
 
 template <class S>
@@ -394,6 +464,22 @@ hipError_t launch_unpack(int storage, const void* st, float* rho, float* u, floa
     case 2: hipLaunchKernelGGL(unpack_kernel<StoreBF16>, dim3(grid), dim3(block), 0, s, (const uint16_t*)st, rho, u, pi, rho_dev, p); break;
     default: return hipErrorInvalidValue;
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_ghost_fold(float* lam, const StepParams& p, const InletParams& q, hipStream_t s) {
+    long long area[6];
+    for (int f = 0; f < 6; ++f) {
+        const int d = f >> 1, d1 = d == 0 ? 1 : 0, d2 = d == 2 ? 1 : 2;
+        area[f] = (q.face_kind[f] == kInlet || q.face_kind[f] == kOutlet) ? (long long)p.geo.n[d1] * p.geo.n[d2] : 0;
+    }
+    long long off[7] = {0};
+    for (int f = 0; f < 6; ++f) off[f + 1] = off[f] + area[f];
+    if (off[6] == 0) return hipSuccess;
+    const int block = 256;
+    const long long grid = (off[6] + block - 1) / block;
+    hipLaunchKernelGGL(ghost_fold_kernel, dim3((unsigned)grid), dim3(block), 0, s, lam, p, q, off[1], off[2], off[3],
+                       off[4], off[5], off[6]);
     return hipGetLastError();
 }
 

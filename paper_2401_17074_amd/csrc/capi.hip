@@ -658,15 +658,16 @@ int tslb_adjoint_seed(tslb_handle h, const void* state, int objective, float* la
     return TSLB_OK;
 }
 
-int tslb_adjoint_step(tslb_handle h, const void* state_t, const void* state_t1, const float* lam_t1, float* lam_t,
+int tslb_adjoint_step(tslb_handle h, const void* state_t, const void* state_t1, float* lam_t1, float* lam_t,
                       float* dg_accum, void* stream) {
     if (!h || !state_t || !state_t1 || !lam_t1 || !lam_t) return fail(TSLB_E_INVALID, "NULL argument");
     if (lam_t == lam_t1) return fail(TSLB_E_INVALID, "lam_t may not alias lam_t1");
     if (h->storage != TSLB_FP32) return fail(TSLB_E_UNSUPPORTED, "the adjoint needs FP32 storage");
-    if (h->has_ghosts) return fail(TSLB_E_UNSUPPORTED, "the adjoint does not differentiate inlet/outlet ghosts");
     if (h->p.order != 3) return fail(TSLB_E_UNSUPPORTED, "the adjoint differentiates the third-order update only");
     if (h->lattice != TSLB_D3Q27) return fail(TSLB_E_UNSUPPORTED, "the adjoint is provided for D3Q27 only");
     DeviceGuard dg(h->device);
+    // the ghost refill of level t+1 first (its transpose, in place)
+    if (h->has_ghosts) HIP_TRY(launch_ghost_fold(lam_t1, h->p, h->inlet, S(stream)));
     if (h->kernel != 1)
         HIP_TRY(launch_adjoint_tiled((const float*)state_t, (const float*)state_t1, lam_t1, lam_t, dg_accum, h->p,
                                      S(stream)));
@@ -705,8 +706,7 @@ int tslb_rollout_backward(tslb_handle h, int nsteps, int every, void* ws, size_t
     if (ws_bytes < tslb_rollout_workspace_bytes(h, nsteps, every)) return fail(TSLB_E_INVALID, "workspace too small");
     if (h->p.order != 3 || h->lattice != TSLB_D3Q27)
         return fail(TSLB_E_UNSUPPORTED, "the adjoint differentiates the third-order D3Q27 update only");
-    if (h->storage != TSLB_FP32 || h->has_ghosts)
-        return fail(TSLB_E_UNSUPPORTED, "the adjoint needs FP32 storage and no inlet/outlet ghosts");
+    if (h->storage != TSLB_FP32) return fail(TSLB_E_UNSUPPORTED, "the adjoint needs FP32 storage");
     DeviceGuard dg(h->device);
     hipStream_t s = S(stream);
     const size_t sb = tslb_state_bytes(h);
@@ -733,6 +733,12 @@ int tslb_rollout_backward(tslb_handle h, int nsteps, int every, void* ws, size_t
         for (int k = 1; k <= len; ++k) {
             h->t = t_end - nsteps + s0 + k - 1;
             HIP_TRY(run_update(h, seg_states + (size_t)(k - 1) * sb, seg_states + (size_t)k * sb, s));
+            h->t += 1;
+            const int rc = fill_ghosts(h, seg_states + (size_t)k * sb, s, true);
+            if (rc) {
+                h->t = t_end;
+                return rc;
+            }
         }
         h->t = t_end;
         for (int k = len - 1; k >= 0; --k) {
@@ -744,6 +750,8 @@ int tslb_rollout_backward(tslb_handle h, int nsteps, int every, void* ws, size_t
             b = tmp;
         }
     }
+    // the initial level's ghosts were refilled from its interior as well
+    if (h->has_ghosts) HIP_TRY(launch_ghost_fold(a, h->p, h->inlet, s));
     if (a != lam) HIP_TRY(hipMemcpyAsync(lam, a, sizeof(float) * 10 * (size_t)h->p.geo.N, hipMemcpyDeviceToDevice, s));
     return TSLB_OK;
 }

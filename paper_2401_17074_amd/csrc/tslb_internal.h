@@ -50,6 +50,9 @@ constexpr int kRedSums = 7;
 hipError_t launch_reduce(int storage, const void* st, double* partials, int nblocks, double* out6,
                          const StepParams& p, hipStream_t s);
 hipError_t launch_stream_copy(const void* src, void* dst, long long n4, hipStream_t s);
+// Transpose of the ghost refill, in place on lam (10 N floats): ghost nodes'
+// sensitivities folded into the interior nodes they copy, then cleared.
+hipError_t launch_ghost_fold(float* lam, const StepParams& p, const InletParams& q, hipStream_t s);
 hipError_t launch_adjoint_seed(const float* st, float* lam, const StepParams& p, int objective, hipStream_t s);
 hipError_t launch_adjoint_step(const float* st0, const float* st1, const float* lam1, float* lam0, float* dg,
                                const StepParams& p, hipStream_t s);

@@ -205,3 +205,60 @@ def test_differentiable_workload_full_size_vs_central_differences():
             print("d/d%s along direction %d: adjoint %.10g central differences %.10g (rel %.2e)"
                   % (name, k, got, fd, abs(got - fd) / abs(fd)))
             assert abs(got - fd) <= 1e-3 * abs(fd)
+
+
+@pytest.mark.parametrize("kernel", [0, 1])
+def test_adjoint_step_through_ghost_layers(kernel):
+    """One adjoint step on a small jet (inlet disc with seeded noise, outflow
+    ghosts on the other faces) against the oracle's: the ghost refill of the
+    new level transposed first (in place on lam_t1), then the update with
+    ghost nodes as ordinary emitters (Section 2.3)."""
+    import torch
+    case = W.jet_case(nx=30, ny=17, nz=14, D=6.0, steps=1)
+    G = oracle_grid(case)
+    kinds = oracle.node_kinds(G)
+    st0 = W.to_fp32(oracle.ghost_fill(G, W.random_state(case.shape, seed=401, u_amp=0.04, pi_amp=1e-3), 0))
+    g = W.random_force(case.shape, seed=402, amp=1e-4).astype(np.float32).astype(np.float64)
+    lam1 = np.random.default_rng(403).standard_normal(st0.shape).astype(np.float32).astype(np.float64)
+    s = gpu_solver(case, kernel=kernel)
+    s.set_force_field(g)
+    s.set_state(to_device_state(st0))
+    raw0 = s.save_raw()
+    s.step(1)
+    raw1 = s.save_raw()
+    lam1_t = torch.tensor(lam1, dtype=torch.float32, device="cuda")
+    dg = torch.zeros((3,) + case.shape, dtype=torch.float32, device="cuda")
+    lam0 = s.adjoint_step(raw0, raw1, lam1_t, dg).double().cpu().numpy()
+    folded = lam1_t.double().cpu().numpy()
+    dg = dg.double().cpu().numpy()
+    s.close()
+    want_lam, want_dg = oracle.adjoint_step(G, st0, lam1, g)
+    assert np.abs(lam0[:, kinds == 2]).max() > 0  # ghost nodes emit
+    assert np.abs(folded[:, kinds == 2]).max() == 0.0  # cleared by the fold
+    assert _rel(lam0, want_lam) < 1e-5
+    assert _rel(dg, want_dg) < 1e-5
+
+
+def test_rollout_gradient_through_ghost_layers():
+    """TslbRollout on a small jet (12 steps, checkpoint every 5) against the
+    oracle's FP64 stored-trajectory gradient, both with the initial ghosts
+    refilled from the interior: dL/dg and dL/du0 (zero on ghost nodes)."""
+    import torch
+    from paper_2401_17074_amd import TslbRollout
+    case = W.jet_case(nx=30, ny=17, nz=14, D=6.0, steps=12)
+    G = oracle_grid(case)
+    kinds = oracle.node_kinds(G)
+    st0 = W.to_fp32(W.random_state(case.shape, seed=404, u_amp=0.04, pi_amp=0.0, rho_amp=0.0))
+    g = W.random_force(case.shape, seed=405, amp=1e-4).astype(np.float32).astype(np.float64)
+    L_or, lam0_or, dg_or = oracle.rollout_grad(G, st0, case.steps, g)
+    s = gpu_solver(case)
+    gt = torch.tensor(g, dtype=torch.float32, device="cuda", requires_grad=True)
+    ut = torch.tensor(st0[1:4], dtype=torch.float32, device="cuda", requires_grad=True)
+    L = TslbRollout.apply(gt, ut, s, case.steps, 5)
+    L.backward()
+    s.close()
+    du = ut.grad.double().cpu().numpy()
+    assert float(L.detach()) == pytest.approx(L_or, rel=1e-5)
+    assert np.abs(du[:, kinds == 2]).max() == 0.0
+    assert _rel(gt.grad.double().cpu().numpy(), dg_or) < 1e-4
+    assert _rel(du, lam0_or[1:4]) < 1e-4
