@@ -117,6 +117,16 @@ __global__ void __launch_bounds__(NTHREADS, TSLB_WAVES_PER_EU) update_tiled_kern
     // 16-bit values right after their loads, or loading 1 - omega when the
     // plane starts, would make the wave wait for its loads at that point.
     typename S::T rcur[10];
+    // With FP32 storage the stored fields are loaded two plane-steps ahead,
+    // into two register sets used in turn (rcur on the even steps of a
+    // segment, rnx on the odd ones): one step of lookahead leaves the kernel
+    // exposed to the HBM latency, which on the 512 x 256 x 256 grids
+    // depends on where the buffers land in memory (up to 20 % slower launches
+    // for some placements).  The 16-bit instantiations (no registers to
+    // spare, compute-bound) and the walls-plus-force-field one (it would
+    // spill) keep one step.
+    constexpr bool kTwo = sizeof(typename S::T) == 4 && !(WALLS && FIELD);
+    typename S::T rnx[kTwo ? 10 : 1];
     float gcur[3] = {0.0f, 0.0f, 0.0f};
     float ocur = p.one_minus_omega;
     auto fetch = [&](unsigned col, int zq) {
@@ -129,8 +139,20 @@ __global__ void __launch_bounds__(NTHREADS, TSLB_WAVES_PER_EU) update_tiled_kern
         if (p.omo_z) ocur = p.omo_z[zq];
     };
 
+    auto fetch_side = [&](unsigned col, int zq) {
+        if constexpr (FIELD) {
+            const unsigned n = col + plane_nodes * (unsigned)zq;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) gcur[a] = ld_at(f.g[a], n * 4u);
+        }
+        if (p.omo_z) ocur = p.omo_z[zq];
+    };
+
     Column c = column(t);
-    if (active) fetch(c.col, plane_index(c.zs - 1, nz, pz));
+    if (active) {
+        fetch(c.col, plane_index(c.zs - 1, nz, pz));
+        if constexpr (kTwo) load_raw<S>(f, c.col + plane_nodes * (unsigned)plane_index(c.zs, nz, pz), rnx);
+    }
 
     for (;;) {
         // the block's next segment: its first plane is loaded while the last
@@ -207,11 +229,14 @@ __global__ void __launch_bounds__(NTHREADS, TSLB_WAVES_PER_EU) update_tiled_kern
         // what arrives from plane zp to the output planes zp - 1 (aprev), zp
         // (acur) and zp + 1 (anext, which starts here), then store the
         // completed plane zp - 1.
-        auto plane = [&](int zp, MomentSums& aprev, MomentSums& acur, MomentSums& anext) {
+        auto plane = [&]<int BUF>(int zp, MomentSums& aprev, MomentSums& acur, MomentSums& anext) {
             float G[27];
             if (active) {
                 float m[10], gl[3];
-                convert_raw<S>(rcur, p, m);
+                if constexpr (kTwo && BUF == 1)
+                    convert_raw<S>(rnx, p, m);
+                else
+                    convert_raw<S>(rcur, p, m);
 #pragma unroll
                 for (int a = 0; a < 3; ++a) gl[a] = FIELD ? gon * gcur[a] : gacc[a];
                 // 1 - omega with the stored Pi^neq scale folded in (see convert_raw)
@@ -250,10 +275,34 @@ __global__ void __launch_bounds__(NTHREADS, TSLB_WAVES_PER_EU) update_tiled_kern
                 // the fetched values are dead once the coefficients are
                 // formed: the next plane's go into the same registers and are
                 // in flight across the exchange, the gather and the stores
+                if constexpr (kTwo) {
+                    // this step's set is free again: load the step after next
+                    // into it, and the next step's force / relaxation values
+                    int c2 = -1, z2 = 0;
+                    if (zp + 2 <= ze) {
+                        c2 = (int)c.col;
+                        z2 = zp + 2;
+                    } else if (tn >= 0) {
+                        c2 = (int)cn.col;
+                        z2 = zp + 2 == ze + 1 ? cn.zs - 1 : cn.zs;
+                    }
+                    if (c2 >= 0) {
+                        const unsigned n2 = (unsigned)c2 + plane_nodes * (unsigned)plane_index(z2, nz, pz);
+                        if constexpr (BUF == 1)
+                            load_raw<S>(f, n2, rnx);
+                        else
+                            load_raw<S>(f, n2, rcur);
+                    }
+                    if (zp + 1 <= ze)
+                        fetch_side(c.col, plane_index(zp + 1, nz, pz));
+                    else if (tn >= 0)
+                        fetch_side(cn.col, plane_index(cn.zs - 1, nz, pz));
+                } else {
                 if (zp + 1 <= ze)
                     fetch(c.col, plane_index(zp + 1, nz, pz));
                 else if (tn >= 0)
                     fetch(cn.col, plane_index(cn.zs - 1, nz, pz));
+                }
             }
             __syncthreads();
             // the 24 values arriving through LDS go to registers at once, so
@@ -341,12 +390,39 @@ __global__ void __launch_bounds__(NTHREADS, TSLB_WAVES_PER_EU) update_tiled_kern
         MomentSums a0, a1, a2;
         a0.zero();
         a1.zero();
+        if constexpr (kTwo) {
+            // accumulator roles repeat every 3 steps, register sets every 2
+            for (int zp = zs - 1; zp <= ze; zp += 6) {
+                plane.template operator()<0>(zp, a0, a1, a2);
+                if (zp + 1 > ze) break;
+                plane.template operator()<1>(zp + 1, a1, a2, a0);
+                if (zp + 2 > ze) break;
+                plane.template operator()<0>(zp + 2, a2, a0, a1);
+                if (zp + 3 > ze) break;
+                plane.template operator()<1>(zp + 3, a0, a1, a2);
+                if (zp + 4 > ze) break;
+                plane.template operator()<0>(zp + 4, a1, a2, a0);
+                if (zp + 5 > ze) break;
+                plane.template operator()<1>(zp + 5, a2, a0, a1);
+            }
+            // an odd number of steps left the next segment's first plane in
+            // rnx: swap the sets so that it starts on rcur again
+            if (((ze - zs) & 1) != 0) {
+#pragma unroll
+                for (int q = 0; q < 10; ++q) {
+                    const typename S::T v = rcur[q];
+                    rcur[q] = rnx[q];
+                    rnx[q] = v;
+                }
+            }
+        } else {
         for (int zp = zs - 1; zp <= ze; zp += 3) {
-            plane(zp, a0, a1, a2);
+            plane.template operator()<0>(zp, a0, a1, a2);
             if (zp + 1 > ze) break;
-            plane(zp + 1, a1, a2, a0);
+            plane.template operator()<0>(zp + 1, a1, a2, a0);
             if (zp + 2 > ze) break;
-            plane(zp + 2, a2, a0, a1);
+            plane.template operator()<0>(zp + 2, a2, a0, a1);
+        }
         }
         if (tn < 0) break;
         ++k;
