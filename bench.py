@@ -127,6 +127,7 @@ def measure_storage_variants(case, st, steps, warmup, kernel, copy_gbs, timed=No
             s = _solver(case, storage, kernel)
             s.set_state(st)
             n_timed = min(max(steps, 50), 200)
+            s.step(max(warmup, 20))
             kms, _ = s.step_timed(n_timed)
             kms /= n_timed
             ms, _ = time_steps(s, steps, warmup)
@@ -562,9 +563,11 @@ def main():
     s.set_state(st_dev)
     # the dominant kernel alone: HIP events around each of its launches, on
     # the stream it runs on (the library's; the default stream here).  Taken
-    # first, so that the whole-step timing below starts on a GPU that has
-    # left its idle clocks (short runs otherwise carry the ramp-up)
+    # after untimed steps and before the whole-step timing, so that neither
+    # measurement starts on a GPU still at its idle clocks (short runs would
+    # otherwise carry the ramp-up)
     n_timed = min(max(args.steps, 50), 200)
+    s.step(max(args.warmup, 20))
     kms, aux_ms = s.step_timed(n_timed)
     ms, wall = time_steps(s, args.steps, args.warmup)
     _, rc = s.reduce(check=False)
