@@ -2,7 +2,9 @@
 // every (tile column, plane) is covered exactly once, segments are
 // non-empty and inside the grid, each block's list is contiguous from its
 // first entry, and the largest block cost equals the reported cost.  Prints
-// one line per case: columns nz resident tz grid nseg cost ideal.
+// one line per case: columns nz resident tz grid nseg cost ideal split, and
+// the number of segments of an odd number of planes that another segment of
+// the same block follows.
 #include <cstdio>
 #include <cstdlib>
 #include <vector>
@@ -14,7 +16,7 @@ using namespace tslb::tile;
 static int check(int columns, int nz, int resident) {
     const Schedule s = build_schedule(columns, nz, resident);
     std::vector<int> seen((size_t)columns * nz, 0);
-    long long worst = 0;
+    long long worst = 0, odd_then_more = 0;
     if (s.grid % 8 != 0 || s.grid > resident || s.nseg < 1 || s.seg.size() != (size_t)s.grid * s.nseg) return 1;
     for (int b = 0; b < s.grid; ++b) {
         long long cost = 0;
@@ -26,6 +28,7 @@ static int check(int columns, int nz, int resident) {
                 continue;
             }
             if (ended) return 2;  // an entry after the end marker
+            if (((q.z - q.y) & 1) && k + 1 < s.nseg && s.seg[(size_t)b * s.nseg + k + 1].x >= 0) ++odd_then_more;
             if (q.x >= columns || q.y < 0 || q.z > nz || q.y >= q.z) return 3;
             for (int z = q.y; z < q.z; ++z) seen[(size_t)q.x * nz + z] += 1;
             cost += q.z - q.y + 2;
@@ -36,7 +39,8 @@ static int check(int columns, int nz, int resident) {
         if (v != 1) return 4;
     if (worst != s.cost) return 5;
     const long long ideal = ((long long)columns * nz + resident - 1) / resident + 2;
-    printf("%d %d %d %d %d %d %lld %lld %d\n", columns, nz, resident, s.tz, s.grid, s.nseg, s.cost, ideal, s.split);
+    printf("%d %d %d %d %d %d %lld %lld %d %lld\n", columns, nz, resident, s.tz, s.grid, s.nseg, s.cost, ideal, s.split,
+           odd_then_more);
     return 0;
 }
 
@@ -44,6 +48,7 @@ int main() {
     const int cases[][3] = {
         {176, 256, 256}, {96, 192, 256}, {344, 512, 256}, {259, 600, 256}, {6, 64, 256}, {1, 1, 256},
         {1, 3, 256},     {2, 1, 8},      {16, 5, 256},    {1376, 1023, 256}, {7, 300, 16}, {33, 17, 40},
+        {20, 457, 256},
     };
     for (const auto& c : cases) {
         const int rc = check(c[0], c[1], c[2]);

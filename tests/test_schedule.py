@@ -29,8 +29,8 @@ def schedule_lines(tmp_path_factory):
 
 
 def test_every_plane_once_and_balanced(schedule_lines):
-    assert len(schedule_lines) == 12
-    for columns, nz, resident, tz, grid, nseg, cost, ideal, split in schedule_lines:
+    assert len(schedule_lines) == 13
+    for columns, nz, resident, tz, grid, nseg, cost, ideal, split, _ in schedule_lines:
         assert 1 <= tz <= 64 and 1 <= split <= 8 and grid % 8 == 0 and grid <= resident
         # within 5 % (plus one segment's halo planes) of the balanced ideal
         assert cost <= 1.05 * ideal + 2, (columns, nz, cost, ideal)
@@ -41,3 +41,11 @@ def test_channel_512x256x256_beats_whole_tile_rounds(schedule_lines):
     # alone need 3 rounds of 66 plane-steps
     row = [r for r in schedule_lines if r[:3] == [176, 256, 256]][0]
     assert row[6] <= 186 < 3 * 66
+
+
+def test_odd_segment_followed_by_another(schedule_lines):
+    # the 256 x 60 x 457 grid of the GPU parity test of the FP32 register-set
+    # swap (20 tile columns): some block marches a segment of an odd number of
+    # planes and then another one
+    row = [r for r in schedule_lines if r[:3] == [20, 457, 256]][0]
+    assert row[9] > 0
