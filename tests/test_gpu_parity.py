@@ -239,25 +239,29 @@ def test_jet_full_size_sampled(kernel):
     assert np.abs(regen[:, gh] - post[:, gh]).max() < 1e-8
 
 
-@pytest.mark.parametrize("name,faces", CASES[:2])
-def test_work_list_odd_segments(name, faces):
+@pytest.mark.parametrize("name,faces,field", [(n, f, False) for n, f in CASES[:2]] + [("periodic_field", CASES[0][1], True)])
+def test_work_list_odd_segments(name, faces, field):
     """A grid whose work list hands blocks a column segment of an odd number
     of planes followed by another segment (256 x 60 x 457: 20 tile columns,
     27-plane tiles, the leftover tiles cut in 3; the CPU schedule test checks
     that such transitions occur): with FP32 storage the tiled update loads
     the stored fields two plane-steps ahead into two register sets used in
-    turn, and such a segment ends on the other set.  One step from a seeded
+    turn, and such a segment ends on the other set; a force field is loaded
+    one step ahead across the same transitions.  One step from a seeded
     random state, every fluid node against the oracle."""
     case = W.Case(name, 256, 60, 457, 0.57, faces=faces)
     st0 = W.to_fp32(W.random_state(case.shape, seed=457))
+    g = W.random_force(case.shape, seed=458, amp=1e-5).astype(np.float32).astype(np.float64) if field else None
     G = oracle_grid(case)
     kinds = oracle.node_kinds(G)
     s = gpu_solver(case, kernel=0)
+    if field:
+        s.set_force_field(g)
     s.set_state(to_device_state(st0))
     s.step(1)
     got = from_device_state(s.get_state())
     s.close()
-    want = oracle.step(G, st0)
+    want = oracle.step(G, st0, g)
     fl = kinds == 0
     assert abs_err(got[0], want[0], fl) < 1e-7
     assert rel_err(got[1:4], want[1:4], fl) < 2e-6
