@@ -528,6 +528,8 @@ def main():
                     help="only run the library's streaming copy of MIB MiB 20 times (HBM counter calibration)")
     ap.add_argument("--summarize-pmc", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "COPY_FETCH_DIR", "COPY_WRITE_DIR"),
                     help="turn four rocprofv3 --pmc output folders into profiles/pmc_<kernel>_<workload>.json")
+    ap.add_argument("--adjoint", type=int, default=0, metavar="N",
+                    help="only the checkpointed-rollout and adjoint-kernel timing on the N^3 forced box (for profiling)")
     ap.add_argument("--oracle-sample", choices=("single_core", "tgv32", "adjoint64"),
                     help="(internal) time one bounded oracle sample on the host and print it as JSON")
     args = ap.parse_args()
@@ -541,6 +543,17 @@ def main():
         print("bench.py measures one GPU: the library runs the update on a single MI355X and has no "
               "multi-GPU path (--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
+    if args.adjoint:
+        import torch
+        torch.cuda.set_device(0)
+        rec = measure_adjoint(args.kernel, n=args.adjoint, nsteps=None if args.adjoint <= 64 else 100)
+        # per node: M_t 40 B, rho' and u' 16 B, lambda_{t+1} 40 B, the force
+        # field 12 B, lambda_t 40 B written, dg read and written 24 B
+        algo = 172 * args.adjoint ** 3
+        rec["adjoint_algorithmic_bytes_per_launch"] = algo
+        rec["adjoint_kernel_gbs"] = round(algo / (rec["adjoint_kernel_ms"] * 1e-3) / 1e9, 1)
+        print(json.dumps(rec))
+        return
     if args.copy_calibration:
         import torch
         from paper_2401_17074_amd import capi as C
