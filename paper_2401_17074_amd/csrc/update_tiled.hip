@@ -18,11 +18,14 @@
 // to moments by the transposed separable sums.
 //
 // Tile = TX x TY interior columns plus a one-node halo ring (extra waves)
-// marching tz planes (plus one halo plane each side), tz chosen per grid at
-// launch; one resident block per CU walks a sequence of tiles.  A plane's emitted
+// marching a segment of planes along z (plus one halo plane each side);
+// one resident block per CU walks its list of segments, built on the host
+// when the handle is created (tile::build_schedule).  A plane's emitted
 // populations with (cx, cy) != (0, 0) go through LDS; the three with
 // cx = cy = 0 stay in the thread.  Contributions to the output planes
-// p - 1, p, p + 1 are accumulated in three rolling register sets.
+// p - 1, p, p + 1 are accumulated in three rolling register sets.  The
+// stored fields are loaded ahead of their use: one plane-step with 16-bit
+// storage, two with FP32 storage.
 #include "tslb_tiles.h"
 
 namespace tslb {
