@@ -82,17 +82,17 @@ def _scaled(st, sc):
     return out
 
 
-@pytest.mark.parametrize("kind", [1, 2])
-@pytest.mark.parametrize("kernel", [0, 1])
-@pytest.mark.parametrize("faces", [(0,) * 6, (0, 0, 1, 1, 0, 0)])
-def test_one_step_within_one_storage_ulp(kind, kernel, faces):
-    case = W.Case("store", 67, 29, 21, 0.61, faces=faces, force=(2e-6, 0.0, 0.0))
+def _one_step_ulp(kind, kernel, faces, field, lattice=27):
+    case = W.Case("store", 67, 29, 21, 0.61, faces=faces, force=(2e-6, 0.0, 0.0), lattice=lattice)
     sc = DEFAULT_SCALES[kind]
     G = oracle_grid(case)
     st0 = oracle.round_storage(G, W.random_state(case.shape, seed=301, u_amp=0.05, pi_amp=2e-3), kind, sc)
     kinds = oracle.node_kinds(G)
     st0[:, kinds == 1] = W.rest_state((1,))[:, 0:1]  # wall nodes hold the rest state
+    g = W.random_force(case.shape, seed=302, amp=2e-6).astype(np.float32).astype(np.float64) if field else None
     s = gpu_solver(case, storage=kind, kernel=kernel)
+    if field:
+        s.set_force_field(g)
     s.set_state(to_device_state(st0))
     back = from_device_state(s.get_state())
     fl = kinds == 0
@@ -100,13 +100,32 @@ def test_one_step_within_one_storage_ulp(kind, kernel, faces):
     s.step(1)
     got = from_device_state(s.get_state())
     s.close()
-    exact = oracle.step(G, st0)
+    exact = oracle.step(G, st0, g)
     want = oracle.round_storage(G, exact, kind, sc)
     g_s, w_s = _scaled(got, sc)[:, fl], _scaled(want, sc)[:, fl]
     diff = np.abs(g_s - w_s)
     bar = _bar(w_s, exact[:, fl], sc, kind)
     assert np.all(diff <= bar), _worst(diff, bar, w_s, g_s, _scaled(exact, sc)[:, fl])
     assert (diff == 0).mean() >= 0.99
+
+
+@pytest.mark.parametrize("field", [False, True])
+@pytest.mark.parametrize("kind", [1, 2])
+@pytest.mark.parametrize("kernel", [0, 1])
+@pytest.mark.parametrize("faces", [(0,) * 6, (0, 0, 1, 1, 0, 0), (1, 1, 0, 0, 1, 1)])
+def test_one_step_within_one_storage_ulp(kind, kernel, faces, field):
+    """One step from a state representable in the 16-bit storage, against
+    the oracle's exact step rounded the same way: periodic, walls on y, walls
+    on x and z, with a uniform force or a per-node force field."""
+    _one_step_ulp(kind, kernel, faces, field)
+
+
+@pytest.mark.parametrize("field", [False, True])
+@pytest.mark.parametrize("kind", [1, 2])
+@pytest.mark.parametrize("faces", [(0,) * 6, (0, 0, 1, 1, 0, 0)])
+def test_d3q19_one_step_within_one_storage_ulp(kind, faces, field):
+    """The same for the D3Q19 update (tiled kernel)."""
+    _one_step_ulp(kind, 0, faces, field, lattice=19)
 
 
 def test_fp64_reductions_match_oracle_sums():
