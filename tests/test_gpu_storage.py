@@ -82,14 +82,20 @@ def _scaled(st, sc):
     return out
 
 
-def _one_step_ulp(kind, kernel, faces, field, lattice=27):
-    case = W.Case("store", 67, 29, 21, 0.61, faces=faces, force=(2e-6, 0.0, 0.0), lattice=lattice)
+def _one_step_ulp(kind, kernel, faces, field, lattice=27, order=3):
+    nz = 1 if lattice == 9 else 21
+    case = W.Case("store", 67, 29, nz, 0.61, faces=faces, force=(2e-6, 0.0, 0.0), lattice=lattice, order=order)
     sc = DEFAULT_SCALES[kind]
     G = oracle_grid(case)
-    st0 = oracle.round_storage(G, W.random_state(case.shape, seed=301, u_amp=0.05, pi_amp=2e-3), kind, sc)
+    st = W.random_state(case.shape, seed=301, u_amp=0.05, pi_amp=2e-3)
+    if lattice == 9:
+        st[[3, 6, 8, 9]] = 0.0  # no z components in two dimensions
+    st0 = oracle.round_storage(G, st, kind, sc)
     kinds = oracle.node_kinds(G)
     st0[:, kinds == 1] = W.rest_state((1,))[:, 0:1]  # wall nodes hold the rest state
     g = W.random_force(case.shape, seed=302, amp=2e-6).astype(np.float32).astype(np.float64) if field else None
+    if g is not None and lattice == 9:
+        g[2] = 0.0
     s = gpu_solver(case, storage=kind, kernel=kernel)
     if field:
         s.set_force_field(g)
@@ -267,3 +273,18 @@ def test_precision_error_report_horizons():
         assert report[("fp32", t)][0] < 1e-3
         assert report[("fp16", t)][0] < 5e-2
         assert report[("bf16", t)][0] < 2e-1
+
+
+@pytest.mark.parametrize("field", [False, True])
+@pytest.mark.parametrize("kind", [1, 2])
+@pytest.mark.parametrize("faces", [(0,) * 6, (0, 0, 1, 1, 0, 0), (1, 1, 1, 1, 0, 0)])
+def test_d2q9_one_step_within_one_storage_ulp(kind, faces, field):
+    """The same for the D2Q9 update."""
+    _one_step_ulp(kind, 0, faces, field, lattice=9)
+
+
+@pytest.mark.parametrize("kind", [1, 2])
+@pytest.mark.parametrize("faces", [(0,) * 6, (0, 0, 1, 1, 0, 0)])
+def test_second_order_one_step_within_one_storage_ulp(kind, faces):
+    """The same for the regularised second-order update (tiled kernel)."""
+    _one_step_ulp(kind, 0, faces, True, order=2)
