@@ -295,6 +295,27 @@ def test_second_order_update_has_no_adjoint():
     s.close()
 
 
+@pytest.mark.parametrize("what", ["fp16", "bf16", "d3q19", "d2q9", "alias"])
+def test_adjoint_rejects_what_it_does_not_differentiate(what):
+    """The adjoint step refuses 16-bit storage, the other lattices
+    (TSLB_E_UNSUPPORTED) and an output aliasing its input (TSLB_E_INVALID),
+    before touching any buffer."""
+    import torch
+    from paper_2401_17074_amd import _binding as C
+    storage = {"fp16": C.TSLB_FP16, "bf16": C.TSLB_BF16}.get(what, C.TSLB_FP32)
+    lattice = {"d3q19": 19, "d2q9": 9}.get(what, 27)
+    case = W.Case("adj_" + what, 16, 12, 1 if lattice == 9 else 10, 0.6, lattice=lattice)
+    s = gpu_solver(case, storage=storage)
+    raw = s.save_raw()
+    lam = torch.ones((10,) + case.shape, dtype=torch.float32, device="cuda")
+    out = torch.full_like(lam, 7.0)
+    with pytest.raises(C.TslbError) as err:
+        C.tslb_adjoint_step(s.h, raw, raw, lam, lam if what == "alias" else out, None)
+    s.close()
+    assert err.value.code == (C.TSLB_E_INVALID if what == "alias" else C.TSLB_E_UNSUPPORTED)
+    assert bool((out == 7.0).all()) and bool((lam == 1.0).all())
+
+
 @pytest.mark.parametrize("kernel", KERNELS)
 def test_timed_steps_match_plain_steps(kernel):
     """tslb_step_timed runs the same launches as tslb_step (bit-identical
