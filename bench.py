@@ -27,6 +27,11 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+# VALU issue ceiling for FP32 arithmetic that is not packed: 256 CUs x 4 SIMDs
+# x 16 lanes x 2.4 GHz, one lane operation per lane and clock (a wave64
+# instruction takes four clocks); the published 157.3 TFLOP/s counts packed
+# FP32 fused multiply-adds, four FLOP per lane and clock
+VALU_PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
 BYTES_PER_FIELD = {0: 4, 1: 2, 2: 2}
 
 
@@ -111,6 +116,14 @@ def kernel_roofline(case, storage, kms_per_launch, kname, copy_gbs):
         rec["frac_of_copy"] = round(achieved / copy_gbs, 4)
     if rec["traffic"]:
         rec["traffic_over_algorithmic"] = round(rec["traffic"] / algo, 4)
+    insts = load_valu(kname, case.name, storage)
+    if insts:
+        # the same launch against the VALU issue ceiling: thread-level VALU
+        # instructions (wave instructions x 64 lanes) per second
+        lane_ops = insts * 64 / (kms_per_launch * 1e-3)
+        rec["valu"] = {"bound": "alu", "achieved": round(lane_ops / 1e12, 2), "peak": round(VALU_PEAK_LANE_OPS / 1e12, 2),
+                       "unit": "T VALU lane-instructions/s", "frac": round(lane_ops / VALU_PEAK_LANE_OPS, 4),
+                       "insts_per_node": round(insts * 64 / case.nodes, 1)}
     return rec
 
 
@@ -378,6 +391,38 @@ def load_traffic(kernel_name, case_name, storage):
     return rec.get("hbm_bytes_per_launch")
 
 
+def load_valu(kernel_name, case_name, storage):
+    """VALU wave instructions per launch (SQ_INSTS_VALU) from the same
+    counter summary, only if it was taken on the current kernel sources."""
+    path = _pmc_path(kernel_name, case_name, storage)
+    if not os.path.exists(path):
+        return None
+    try:
+        rec = json.load(open(path))
+    except ValueError:
+        return None
+    if rec.get("source_hash") != _source_hash() or rec.get("storage") != storage:
+        return None
+    return rec.get("valu_insts_per_dispatch")
+
+
+def summarize_valu(args):
+    """Add SQ_INSTS_VALU per update launch (a rocprofv3 --pmc run of its own)
+    to the counter summary of the same workload and storage."""
+    kname = ("update_tiled", "update_direct", "push")[args.kernel]
+    insts, n = _counter_mean(args.summarize_valu, "SQ_INSTS_VALU", kname + "_kernel")
+    import workloads as W
+    case, _ = WORKLOADS[args.workload](W)
+    path = _pmc_path(kname, case.name, args.storage)
+    rec = json.load(open(path))
+    if rec.get("source_hash") != _source_hash():
+        raise SystemExit("%s was taken on other kernel sources" % path)
+    rec["valu_insts_per_dispatch"] = insts
+    rec["valu_dispatches"] = n
+    json.dump(rec, open(path, "w"), indent=1)
+    print(json.dumps(rec))
+
+
 def _counter_mean(folder, counter, name_part):
     import csv
     import glob
@@ -528,6 +573,8 @@ def main():
                     help="only run the library's streaming copy of MIB MiB 20 times (HBM counter calibration)")
     ap.add_argument("--summarize-pmc", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "COPY_FETCH_DIR", "COPY_WRITE_DIR"),
                     help="turn four rocprofv3 --pmc output folders into profiles/pmc_<kernel>_<workload>.json")
+    ap.add_argument("--summarize-valu", metavar="VALU_DIR",
+                    help="add SQ_INSTS_VALU per launch from a rocprofv3 --pmc output folder to the counter summary")
     ap.add_argument("--adjoint", type=int, default=0, metavar="N",
                     help="only the checkpointed-rollout and adjoint-kernel timing on the N^3 forced box (for profiling)")
     ap.add_argument("--oracle-sample", choices=("single_core", "tgv32", "adjoint64"),
@@ -538,6 +585,9 @@ def main():
         return
     if args.summarize_pmc:
         summarize_pmc(args)
+        return
+    if args.summarize_valu:
+        summarize_valu(args)
         return
     if args.gpus != 1:
         print("bench.py measures one GPU: the library runs the update on a single MI355X and has no "

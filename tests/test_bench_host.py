@@ -54,3 +54,25 @@ def test_more_than_one_gpu_is_refused():
                        text=True, timeout=120)
     assert r.returncode == 2
     assert "one GPU" in r.stderr
+
+
+def test_valu_view_of_the_roofline(monkeypatch, tmp_path):
+    """A counter summary that carries SQ_INSTS_VALU adds the VALU view:
+    thread-level instructions per second against the non-packed FP32 issue
+    ceiling (256 CUs x 64 lanes x 2.4 GHz), only on the current sources."""
+    case = W.channel_case(nx=512, ny=256, nz=256)
+    path = tmp_path / "pmc.json"
+    rec = {"storage": 1, "source_hash": bench._source_hash(), "hbm_bytes_per_launch": 1.4e9,
+           "valu_insts_per_dispatch": 166969448.0}
+    path.write_text(json.dumps(rec))
+    monkeypatch.setattr(bench, "_pmc_path", lambda k, c, s: str(path))
+    roof = bench.kernel_roofline(case, 1, 0.4358, "update_tiled", 5900.0)
+    v = roof["valu"]
+    assert v["bound"] == "alu" and abs(v["peak"] - 39.32) < 0.01
+    lane_ops = 166969448.0 * 64 / 0.4358e-3
+    assert abs(v["achieved"] - lane_ops / 1e12) < 0.01
+    assert abs(v["frac"] - lane_ops / (256 * 64 * 2.4e9)) < 1e-4
+    assert abs(v["insts_per_node"] - 166969448.0 * 64 / case.nodes) < 0.1
+    rec["source_hash"] = "0" * 16
+    path.write_text(json.dumps(rec))
+    assert "valu" not in bench.kernel_roofline(case, 1, 0.4358, "update_tiled", 5900.0)
