@@ -147,10 +147,12 @@ def _sampled_one_step(case, st_pre, got_post, nsamp, seed):
 
 
 @pytest.mark.parametrize("kernel", KERNELS)
-def test_channel_full_size_sampled(kernel):
-    """384x192x192 channel (walls at y = 0, ny - 1), the benchmark launch:
-    20 steps, then one more step checked at 4000 sampled fluid nodes."""
-    case = W.channel_case()
+@pytest.mark.parametrize("dims", [(384, 192, 192), (512, 256, 256)])
+def test_channel_full_size_sampled(kernel, dims):
+    """The 384x192x192 channel and the 512x256x256 one that the benchmark
+    times (walls at y = 0, ny - 1), in the launch configuration the benchmark
+    uses: 20 steps, then one more step checked at 4000 sampled fluid nodes."""
+    case = W.channel_case(nx=dims[0], ny=dims[1], nz=dims[2])
     st0 = W.to_fp32(W.channel_state(case))
     s = gpu_solver(case, kernel=kernel)
     s.set_state(to_device_state(st0))
